@@ -1,0 +1,328 @@
+"""Plain FP64 reference of the truncated-EM sparse-coding learners.
+
+TEST INFRASTRUCTURE.  This file is the oracle that the GPU library is checked
+against.  Only the test-suite, the smoke check and the benchmark's CPU
+baseline leg may import it; the product path never does, and the two share
+no code.  Everything here is written for obviousness, not speed: every
+log-joint is evaluated from its definition with the *direct* residual
+||y - f(s)||^2 and library routines (matrix product, logsumexp, linear solve)
+are the only building blocks.
+
+What is computed (ProSper, "Learning Algorithm and Data Models", Eq. 1-2,
+Table 1; truncated posteriors per the same section and the introduction):
+
+* generative model  p(s | Theta) p(y | s, Theta) with Gaussian noise of
+  standard deviation sigma and mean f(Theta, s):
+    - BSC: s in {0,1}^H, Bernoulli(pi) prior, f = W s
+    - TSC: s in {-1,0,1}^H, P(+-1) = pi/2, P(0) = 1 - pi, f = W s
+    - MCA: s in {0,1}^H, Bernoulli(pi) prior, f_d = max_h s_h W_dh
+* E-step with truncated posteriors: per data point a set I_n of H' latents is
+  preselected ("Hprime" of the API section), the state set K_n holds every
+  state whose support lies in I_n with at most gamma non-zero entries
+  ("gamma" of the API section), and q_n(s) is the exact posterior
+  renormalised on K_n.
+* M-step: the joint maximiser of sum_n sum_s q_n(s) log p(y_n, s | Theta).
+
+Readings where the paper is silent (each listed in the design notes):
+  selection score = singleton log-joint, ties to the lower index, points
+  flagged when the H'-th and (H'+1)-th scores lie within 1e-6 relative;
+  canonical state order = (number of active slots, lexicographic slot
+  tuple, TSC sign pattern in binary counting order);
+  MCA M-step = hard-max responsibilities (limit of the smooth max), sigma
+  from the old W in the same sweep.
+
+Parity pins: see tests/test_oracle_*.py (brute force over all states with
+scipy's multivariate normal, closed forms at H = 1, MCA == BSC special cases,
+posterior invariants, textbook least squares, the EM monotonicity theorem,
+bars recovery).
+"""
+from __future__ import annotations
+
+from itertools import combinations
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+from scipy.special import logsumexp
+
+__all__ = [
+    "BSC", "TSC", "MCA", "MODELS", "TIE_REL",
+    "state_table", "state_masks", "log_prior", "superposition", "log_joint",
+    "selection_scores", "preselect", "estep_point", "estep", "mstep",
+    "em_run", "free_energy",
+]
+
+BSC, TSC, MCA = "bsc", "tsc", "mca"
+MODELS = (BSC, TSC, MCA)
+TIE_REL = 1e-6  # selection boundary flag band (relative, floor 1)
+
+
+# --------------------------------------------------------------------------
+# truncated state set K (API section: Hprime, gamma)
+# --------------------------------------------------------------------------
+def state_table(model: str, Hp: int, gamma: int) -> List[Tuple[Tuple[int, ...], Tuple[int, ...]]]:
+    """All states with support inside the H' slots and at most gamma actives.
+
+    A state is (slots, values): ascending slot indices j in [0, H') and the
+    value of each active slot (+1 for BSC/MCA; +-1 for TSC).
+    Canonical order: k ascending; slot tuples lexicographically; for TSC the
+    sign patterns of one support in binary counting order, bit i of the
+    counter giving the sign of the i-th active slot (0 -> +1, 1 -> -1).
+    """
+    out = []
+    for k in range(0, min(gamma, Hp) + 1):
+        for slots in combinations(range(Hp), k):
+            if model == TSC:
+                for code in range(1 << k):
+                    vals = tuple(-1 if (code >> i) & 1 else 1 for i in range(k))
+                    out.append((slots, vals))
+            else:
+                out.append((slots, (1,) * k))
+    return out
+
+
+def state_masks(model: str, Hp: int, gamma: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Bit masks of the canonical table: active[k] has bit j set iff slot j is
+    active; sign[k] has bit j set iff slot j holds -1."""
+    tab = state_table(model, Hp, gamma)
+    act = np.zeros(len(tab), dtype=np.uint32)
+    sgn = np.zeros(len(tab), dtype=np.uint32)
+    for i, (slots, vals) in enumerate(tab):
+        for j, v in zip(slots, vals):
+            act[i] |= np.uint32(1 << j)
+            if v < 0:
+                sgn[i] |= np.uint32(1 << j)
+    return act, sgn
+
+
+def _embed(tab, sel: Sequence[int], H: int) -> np.ndarray:
+    """States of the table as full H-vectors (rows), slots mapped through sel."""
+    S = np.zeros((len(tab), H))
+    for i, (slots, vals) in enumerate(tab):
+        for j, v in zip(slots, vals):
+            S[i, sel[j]] = v
+    return S
+
+
+# --------------------------------------------------------------------------
+# the generative model (Eq. 1 prior, Eq. 2 Gaussian noise around f(Theta, s))
+# --------------------------------------------------------------------------
+def log_prior(model: str, S: np.ndarray, pi: float) -> np.ndarray:
+    """log p(s | Theta) for every row of S (sum over latents of log p(s_h))."""
+    nz = (S != 0)
+    if model == TSC:
+        per = np.where(nz, np.log(pi / 2.0), np.log1p(-pi))
+    else:
+        per = np.where(nz, np.log(pi), np.log1p(-pi))
+    return per.sum(axis=-1)
+
+
+def superposition(model: str, W: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """f(Theta, s) for every row of S: W s (linear) or max_h s_h W_dh (MCA)."""
+    if model == MCA:
+        return (S[:, None, :] * W[None, :, :]).max(axis=2)
+    return S @ W.T
+
+
+def log_joint(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
+              S: np.ndarray) -> np.ndarray:
+    """log p(y, s | Theta) for every row s of S, with the direct residual."""
+    D = y.shape[0]
+    R = y[None, :] - superposition(model, W, S)
+    sq = (R * R).sum(axis=1)
+    return (log_prior(model, S, pi)
+            - 0.5 * D * np.log(2.0 * np.pi * sigma * sigma)
+            - sq / (2.0 * sigma * sigma))
+
+
+# --------------------------------------------------------------------------
+# preselection of H' latents
+# --------------------------------------------------------------------------
+def selection_scores(model: str, y: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """r_h = 1/2||y||^2 - 1/2||y - f(e_h)||^2 (the singleton log-joint up to
+    h-independent terms and the positive factor 1/sigma^2); for TSC the better
+    of the two signs."""
+    H = W.shape[1]
+    E = np.eye(H)
+    yy = 0.5 * float(y @ y)
+    R = y[None, :] - superposition(model, W, E)
+    r = yy - 0.5 * (R * R).sum(axis=1)
+    if model == TSC:
+        Rm = y[None, :] - superposition(model, W, -E)
+        r = np.maximum(r, yy - 0.5 * (Rm * Rm).sum(axis=1))
+    return r
+
+
+def preselect(r: np.ndarray, Hp: int, tie_rel: float = TIE_REL) -> Tuple[np.ndarray, bool]:
+    """The H' largest scores, ties to the lower index, returned ascending.
+    Flagged when the H'-th and (H'+1)-th largest scores are within tie_rel
+    (relative to max(1, |r_(H')|))."""
+    H = r.shape[0]
+    order = sorted(range(H), key=lambda h: (-r[h], h))
+    sel = np.array(sorted(order[:Hp]), dtype=np.int64)
+    flagged = False
+    if Hp < H:
+        a, b = r[order[Hp - 1]], r[order[Hp]]
+        flagged = bool(abs(a - b) <= tie_rel * max(1.0, abs(a)))
+    return sel, flagged
+
+
+# --------------------------------------------------------------------------
+# E-step
+# --------------------------------------------------------------------------
+def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
+                Hp: int, gamma: int, topk: int = 0, tab=None) -> Dict:
+    """Truncated posterior of one data point (all float64)."""
+    y = np.asarray(y, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    H = W.shape[1]
+    r = selection_scores(model, y, W)
+    sel, flagged = preselect(r, Hp)
+    if tab is None:
+        tab = state_table(model, Hp, gamma)
+    S = _embed(tab, sel, H)                      # |K| x H
+    lj = log_joint(model, y, W, pi, sigma, S)    # |K|
+    logL = float(logsumexp(lj))
+    q = np.exp(lj - logL)
+    Ss = S[:, sel]                               # |K| x H' (values per slot)
+    s_mean = q @ Ss
+    ss_mean = (Ss * q[:, None]).T @ Ss
+    k = (Ss != 0).sum(axis=1)
+    out = dict(sel=sel, flagged=flagged, scores=r, lj=lj, q=q, logL=logL,
+               s_mean=s_mean, ss_mean=ss_mean, k_mean=float(q @ k))
+    if topk:
+        idx = np.arange(len(tab))
+        order = np.lexsort((idx, -q))[:topk]
+        out["top_index"] = order
+        out["top_q"] = q[order]
+    if model == MCA:
+        # responsibilities: R[d, j] = sum_s q(s) [slot j is the lowest-index
+        # active slot attaining the max of W_d over the active set, and that
+        # max is > 0]
+        Wc = W[:, sel]
+        R = np.zeros((W.shape[0], Hp))
+        res = y[None, :] - superposition(model, W, S)
+        for i, (slots, _vals) in enumerate(tab):
+            if not slots:
+                continue
+            sub = Wc[:, list(slots)]
+            am = np.argmax(sub, axis=1)
+            mx = sub[np.arange(sub.shape[0]), am]
+            pos = mx > 0
+            R[np.nonzero(pos)[0], np.array(slots)[am[pos]]] += q[i]
+        out["R"] = R
+        out["res_mean"] = float(q @ (res * res).sum(axis=1))
+    return out
+
+
+def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
+          Hp: int, gamma: int, topk: int = 0, keep_posterior: bool = False) -> Dict:
+    """Truncated E-step over all points, plus the M-step accumulators.
+
+    Returns per-point arrays (sel, flagged, logL, s_mean, ss_mean, k_mean,
+    top_index, top_q) and the sums
+      BSC/TSC: A = sum y <s>^T (D x H), B = sum <ss^T> (H x H)
+      MCA:     A = sum R * y (D x H),   B = sum R (D x H)
+      scal = [sum <k>, sum logL, sum ||y||^2, sum <||y - f(s)||^2> (MCA), N]
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    N, D = Y.shape
+    H = W.shape[1]
+    tab = state_table(model, Hp, gamma)
+    sel = np.zeros((N, Hp), dtype=np.int64)
+    flagged = np.zeros(N, dtype=bool)
+    logL = np.zeros(N)
+    s_mean = np.zeros((N, Hp))
+    ss_mean = np.zeros((N, Hp, Hp))
+    k_mean = np.zeros(N)
+    top_index = np.zeros((N, topk), dtype=np.int64)
+    top_q = np.zeros((N, topk))
+    A = np.zeros((D, H))
+    B = np.zeros((H, H)) if model != MCA else np.zeros((D, H))
+    res_sum = 0.0
+    post = []
+    for n in range(N):
+        p = estep_point(model, Y[n], W, pi, sigma, Hp, gamma, topk, tab)
+        sel[n], flagged[n], logL[n] = p["sel"], p["flagged"], p["logL"]
+        s_mean[n], ss_mean[n], k_mean[n] = p["s_mean"], p["ss_mean"], p["k_mean"]
+        if topk:
+            top_index[n], top_q[n] = p["top_index"], p["top_q"]
+        c = p["sel"]
+        if model == MCA:
+            A[:, c] += p["R"] * Y[n][:, None]
+            B[:, c] += p["R"]
+            res_sum += p["res_mean"]
+        else:
+            A[:, c] += np.outer(Y[n], p["s_mean"])
+            B[np.ix_(c, c)] += p["ss_mean"]
+        if keep_posterior:
+            post.append((c, p["q"]))
+    scal = np.array([k_mean.sum(), logL.sum(), float((Y * Y).sum()), res_sum, float(N)])
+    out = dict(sel=sel, flagged=flagged, logL=logL, s_mean=s_mean, ss_mean=ss_mean,
+               k_mean=k_mean, top_index=top_index, top_q=top_q, A=A, B=B, scal=scal,
+               table=tab)
+    if keep_posterior:
+        out["posterior"] = post
+    return out
+
+
+def free_energy(est: Dict) -> float:
+    """Truncated free energy sum_n log sum_{s in K_n} p(y_n, s | Theta)."""
+    return float(est["scal"][1])
+
+
+# --------------------------------------------------------------------------
+# M-step: joint maximiser of sum_n sum_s q_n(s) log p(y_n, s | Theta)
+# --------------------------------------------------------------------------
+def mstep(model: str, Y: np.ndarray, W_old: np.ndarray, est: Dict,
+          Hp: int = None, gamma: int = None):
+    """New (W, pi, sigma) from one E-step's statistics.
+
+    BSC/TSC: W = A B^-1 on the latents with B_hh > 0 (others keep their old
+    column); pi = sum<k>/(N H); sigma^2 = sum_n sum_s q ||y - W_new s||^2/(N D)
+    as a direct second sweep over each K_n (needs keep_posterior=True).
+    MCA: W_dh = sum R y / sum R (zero denominator keeps the old value);
+    pi as BSC; sigma^2 = sum_n sum_s q ||y - f_{W_old}(s)||^2 / (N D).
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    W_old = np.asarray(W_old, dtype=np.float64)
+    N, D = Y.shape
+    H = W_old.shape[1]
+    A, B, scal = est["A"], est["B"], est["scal"]
+    pi_new = scal[0] / (N * H)
+    W_new = W_old.copy()
+    if model == MCA:
+        pos = B > 0
+        W_new[pos] = A[pos] / B[pos]
+        sigma2 = scal[3] / (N * D)
+    else:
+        act = np.diag(B) > 0
+        if act.any():
+            Bact = B[np.ix_(act, act)]
+            W_new[:, act] = np.linalg.solve(Bact, A[:, act].T).T
+        tab = est["table"]
+        tot = 0.0
+        for n, (c, q) in enumerate(est["posterior"]):
+            S = _embed(tab, c, H)
+            R = Y[n][None, :] - S @ W_new.T
+            tot += float(q @ (R * R).sum(axis=1))
+        sigma2 = tot / (N * D)
+    return W_new, float(pi_new), float(np.sqrt(sigma2))
+
+
+def em_run(model: str, Y: np.ndarray, W0: np.ndarray, pi0: float, sigma0: float,
+           Hp: int, gamma: int, iters: int, callback=None):
+    """Plain EM loop: E-step at Theta_t, M-step to Theta_{t+1}.
+
+    Returns the list of free energies F(Theta_t) (t = 0..iters-1) and the
+    final parameters.
+    """
+    W, pi, sigma = np.asarray(W0, dtype=np.float64), float(pi0), float(sigma0)
+    F = []
+    for it in range(iters):
+        est = estep(model, Y, W, pi, sigma, Hp, gamma, keep_posterior=(model != MCA))
+        F.append(free_energy(est))
+        W, pi, sigma = mstep(model, Y, W, est)
+        if callback is not None:
+            callback(it, W, pi, sigma, est)
+    return F, W, pi, sigma
