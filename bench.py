@@ -1,0 +1,319 @@
+#!/usr/bin/env python3
+"""Benchmark of the truncated E-step at BSC scale on one MI355X.
+
+Workload: BSC, D = H = 256, N = 200000 points, H' = 12, gamma = 4
+(|K| = 794 states per point), synthetic data from the generative model
+(Gaussian unit-norm dictionary, pi = 5/256, sigma = 0.5).
+
+One step = one EM iteration on the device: clear the accumulators, the
+truncated E-step with statistic accumulation (parameter prep, projection +
+preselection, state walk, A accumulation) and the FP64 M-step, with W, pi
+and sigma staying in device memory.  The metric is joint evaluations per
+second: N |K| per step over the measured step time.  The BF16 form (split
+BF16 MFMA projection) gives `value`; the plain FP32 form is reported beside
+it, each with its error against the FP64 oracle on a sample.
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus 1.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # FP32 lane-op slots/s, non-packed: 39.3 T
+
+
+def state_walk_ops(Hp: int, gamma: int) -> int:
+    """Algorithmic VALU op slots per point of the unrolled walk (BSC).
+
+    Per non-zero state: its log-joint from the parent's (1 add), the weight
+    2^(lj - m) (1 sub + 1 transcendental at quarter rate = 4 slots), the
+    subtree sum into the parent (1 add), <s_j> (1 add), <s_i s_j> for the
+    k-1 earlier slots (k-1 adds).  Per state below depth 1: one entry of its
+    parent's w vector (1 add).  Pivot walk over the states with <= 2 actives:
+    1 add + 1 max each."""
+    ops = 0
+    for k in range(1, gamma + 1):
+        c = math.comb(Hp, k)
+        ops += c * (1 + 1 + 4 + 1 + 1 + (k - 1))
+        if k >= 2:
+            ops += c
+        if k <= 2:
+            ops += c * 2
+    return ops
+
+
+def cpu_oracle_baseline(Y, W, pi, sigma, Hp, gamma, target_s):
+    """Time the FP64 oracle on a bounded sample with a process pool."""
+    import concurrent.futures as cf
+    import numpy as np
+    from oracle import prosper_oracle as O
+    cores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    O.estep("bsc", Y[:8], W, pi, sigma, Hp, gamma)
+    per_pt = (time.perf_counter() - t0) / 8
+    n = int(max(cores * 8, min(Y.shape[0], target_s * cores / max(per_pt, 1e-6) / 1.5)))
+    n = min(n, Y.shape[0])
+    idx = np.sort(np.random.default_rng(11).choice(Y.shape[0], n, replace=False))
+    chunks = np.array_split(idx, cores)
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=cores, initializer=_one_thread) as ex:
+        parts = list(ex.map(_oracle_chunk, [(Y[c], W, pi, sigma, Hp, gamma) for c in chunks]))
+    wall = time.perf_counter() - t0
+    ref = {k: np.concatenate([p[k] for p in parts]) for k in ("sel", "s_mean", "logL", "flagged")}
+    return idx, ref, wall, cores
+
+
+def _one_thread():
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _oracle_chunk(a):
+    from oracle import prosper_oracle as O
+    Yc, W, pi, sigma, Hp, gamma = a
+    r = O.estep("bsc", Yc, W, pi, sigma, Hp, gamma)
+    return {k: r[k] for k in ("sel", "s_mean", "logL", "flagged")}
+
+
+def error_stats(g, r):
+    import numpy as np
+    same = np.all(g["sel"] == r["sel"], axis=1)
+    fl = np.asarray(r["flagged"], dtype=bool)
+    use = same & ~fl
+    es = (np.abs(g["s_mean"][use] - r["s_mean"][use]).max(1)
+          / np.maximum(np.abs(r["s_mean"][use]).max(1), 1e-3))
+    el = np.abs(g["logL"][use].astype(np.float64) - r["logL"][use]) / np.maximum(np.abs(r["logL"][use]), 1)
+    return {"points": int(len(same)), "flagged": int(fl.sum()),
+            "sel_mismatch": int((~same & ~fl).sum()),
+            "s_mean_rel_max": float(es.max()), "s_mean_rel_p999": float(np.quantile(es, 0.999)),
+            "logL_rel_max": float(el.max())}
+
+
+def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
+    """Warm up, then time `steps` EM iterations; returns (ms/step, profile)."""
+    Wd = W0.clone()
+    theta = theta0.clone()
+    acc = api.new_acc("bsc", wl.D, wl.H)
+
+    def step():
+        api.zero_acc(acc)
+        api.estep(Yd, Wd, Hprime=wl.Hprime, gamma=wl.gamma, precision=prec, theta=theta,
+                  acc=acc, want=(), ctx=ctx)
+        api.mstep(acc, Wd, model="bsc", W_new=Wd, theta_new=theta, ctx=ctx)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lib = api._lib.load()
+    lib.prosper_profile(ctx.handle, 1)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ev_ms = start.elapsed_time(stop)
+    import ctypes as C
+    cap = 16
+    names = (C.c_char_p * cap)()
+    tot = (C.c_double * cap)()
+    cnt = (C.c_int64 * cap)()
+    k = lib.prosper_profile_read(ctx.handle, cap, names, tot, cnt)
+    prof = {names[i].decode(): {"ms": tot[i], "launches": cnt[i]} for i in range(min(k, cap))}
+    lib.prosper_profile(ctx.handle, 0)
+    return max(ev_ms, 1e-9) / steps, wall_ms / steps, prof, Wd, theta
+
+
+def serving_bench(np, api, n_req, prec):
+    import threading
+    import synth
+    from paper_1908_06843_amd.serve import Server
+    wl = synth.WORKLOADS["serve"]
+    g = synth.rng(wl.data_seed)
+    W = synth.unit_norm_gaussian_dictionary(g, wl.D, wl.H).astype(np.float32)
+    sizes, mix = synth.serving_requests(n_req, seed=wl.data_seed)
+    reqs = []
+    for n, (hp, gm) in zip(sizes, mix):
+        S = synth.sample_binary(g, int(n), wl.H, wl.pi)
+        reqs.append((synth.linear_observations(g, W.astype(np.float64), S, wl.sigma).astype(np.float32), hp, gm))
+    srv = Server(W, wl.pi, wl.sigma, precision=prec, mem_budget_bytes=1 << 30, max_inflight=32,
+                 n_streams=4)
+    # warm-up (tables, code paths)
+    for hp, gm in ((8, 3), (10, 4), (12, 5)):
+        rid, _ = srv.submit(reqs[0][0][:4], hp, gm)
+        srv.wait(rid)
+    # saturated throughput: everything queued at once
+    t0 = time.perf_counter()
+    ids = [srv.submit(Y, hp, gm)[0] for Y, hp, gm in reqs]
+    for rid in ids:
+        srv.wait(rid)
+    sat_s = time.perf_counter() - t0
+    sat_rate = len(reqs) / sat_s
+    patches = int(sum(Y.shape[0] for Y, _, _ in reqs))
+    # Poisson arrivals at 80% of the saturated request rate
+    lam = 0.8 * sat_rate
+    gaps = g.exponential(1.0 / lam, len(reqs))
+    lat = [0.0] * len(reqs)
+    ids2 = [None] * len(reqs)
+    done = threading.Event()
+
+    def waiter():
+        for i in range(len(reqs)):
+            while ids2[i] is None:
+                time.sleep(5e-5)
+            lat[i] = srv.wait(ids2[i])
+        done.set()
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    t_next = t0
+    for i, (Y, hp, gm) in enumerate(reqs):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            pass
+        ids2[i] = srv.submit(Y, hp, gm)[0]
+    th.join()
+    load_s = time.perf_counter() - t0
+    srv.stop()
+    lat = np.array(lat)
+    return {"requests": len(reqs), "patches": patches,
+            "saturated_patches_per_s": patches / sat_s,
+            "offered_load": "poisson at 0.8x saturated request rate",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "patches_per_s": patches / load_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   "the multi-GPU data-parallel path is a design, not a build"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_1908_06843_amd import api
+
+    wl = synth.WORKLOADS["bsc256"]
+    Y, Wgt, _, _ = synth.make_workload("bsc256")
+    W0, pi0, s0 = synth.initial_params(wl, Y)
+    K = api.state_count("bsc", wl.Hprime, wl.gamma)
+    dev = torch.device("cuda", 0)
+    ctx = api.context(0)
+    Yd = torch.tensor(Y, device=dev)
+    W0d = torch.tensor(W0, device=dev)
+    theta0 = torch.tensor([pi0, s0], dtype=torch.float64, device=dev)
+
+    res = {}
+    for prec in (["bf16"] if args.no_fp32 else ["bf16", "fp32"]):
+        ms, wall_ms, prof, Wfin, thfin = run_em_steps(api, torch, Yd, W0d, theta0, wl, prec,
+                                                      args.steps, args.warmup, ctx)
+        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "profile": prof}
+        print(f"# {prec}: {ms:.3f} ms/step  " +
+              "  ".join(f"{k} {v['ms'] / v['launches'] * 1e3:.1f}us" for k, v in prof.items()),
+              file=sys.stderr, flush=True)
+
+    # errors against the FP64 oracle at fixed parameters (learning init), on the
+    # same bounded sample the CPU baseline times
+    cpu = None
+    err = {}
+    if not args.no_cpu:
+        idx, ref, wall, cores = cpu_oracle_baseline(Y, W0, pi0, s0, wl.Hprime, wl.gamma,
+                                                    args.cpu_seconds)
+        cpu = {"value": len(idx) * K / wall, "unit": "joint evals/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{len(idx)} of {Y.shape[0]} points (seeded), full E-step per point, "
+                         f"{wall:.1f} s wall on {cores} processes x 1 BLAS thread"}
+        for prec in res:
+            out = api.estep(Yd, W0d, pi0, s0, Hprime=wl.Hprime, gamma=wl.gamma, precision=prec,
+                            ctx=ctx)
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
+            err[prec] = error_stats(g, ref)
+
+    # roofline of the dominant kernel group of the BF16 step
+    prof = res["bf16"]["profile"]
+    dom = max((k for k in prof if k != "mstep"), key=lambda k: prof[k]["ms"])
+    per_launch_ms = prof[dom]["ms"] / prof[dom]["launches"]
+    N = Y.shape[0]
+    if dom == "states_lin":
+        work = N * state_walk_ops(wl.Hprime, wl.gamma)
+        roof = {"bound": "alu", "achieved": work / (per_launch_ms * 1e-3) / 1e12,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
+    elif dom == "project_select":
+        work = 2.0 * N * wl.D * wl.H
+        roof = {"bound": "mfma", "achieved": work / (per_launch_ms * 1e-3) / 1e12,
+                "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s"}
+    else:
+        work = N * wl.D * 4.0
+        roof = {"bound": "hbm", "achieved": work / (per_launch_ms * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["kernel_us"] = per_launch_ms * 1e3
+
+    serving = None
+    if not args.no_serve:
+        serving = {p: serving_bench(np, api, args.serve_requests, p) for p in ("bf16", "fp32")}
+
+    ms = res["bf16"]["ms_per_step"]
+    line = {
+        "metric": "truncated E-step joint evals/s",
+        "value": N * K / (ms * 1e-3),
+        "unit": "joint evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic (BSC generative model, seeded)",
+        "config": {"workload": "BSC at scale: D=256 H=256 N=200000 H'=12 gamma=4 |K|=794, "
+                               "one EM iteration (E-step with statistics + FP64 M-step)",
+                   "D": wl.D, "H": wl.H, "N": N, "Hprime": wl.Hprime, "gamma": wl.gamma,
+                   "states": K, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": {p: {"value": N * K / (r["ms_per_step"] * 1e-3),
+                      "ms_per_step": r["ms_per_step"],
+                      "estep_ms": sum(v["ms"] for k, v in r["profile"].items() if k != "mstep")
+                      / args.steps,
+                      "kernel_us": {k: v["ms"] / v["launches"] * 1e3
+                                    for k, v in r["profile"].items()},
+                      "error_vs_fp64_oracle": err.get(p)} for p, r in res.items()},
+        "serving": serving,
+    }
+    if "fp32" in res:
+        line["bf16_speedup_over_fp32"] = res["fp32"]["ms_per_step"] / ms
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * prosper.h -- C ABI of the MI355X truncated-EM sparse-coding library.
+ *
+ * The library computes the truncated E-step (and the M-step it feeds) of the
+ * probabilistic sparse-coding learners described in ProSper (Exarchakis et
+ * al.), section "Learning Algorithm and Data Models":
+ *
+ *   prior          p(s | Theta)          (Eq. 1)
+ *   noise model    p(y | s, Theta) = N(y; f(Theta, s), sigma^2 I)   (Eq. 2)
+ *
+ * with the model family of Table 1:
+ *   PROSPER_BSC  s in {0,1}^H,    Bernoulli(pi),           f = W s
+ *   PROSPER_TSC  s in {-1,0,1}^H, P(+-1) = pi/2 each,      f = W s
+ *   PROSPER_MCA  s in {0,1}^H,    Bernoulli(pi),           f_d = max_h s_h W_dh
+ *
+ * Truncated posteriors (same section): for each data point y_n the library
+ * preselects H' latents I_n (the "Hprime" argument of the API section) and
+ * renormalises the exact posterior on
+ *   K_n = { s : s_h = 0 for h not in I_n, and #nonzero(s) <= gamma }
+ * ("gamma" of the API section).  |K_n| = sum_{k<=gamma} C(H',k) (V-1)^k with
+ * V = 2 (BSC, MCA) or 3 (TSC).
+ *
+ * Conventions (all entry points)
+ *  - Every device pointer is owned by the caller; the library never frees one.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on it; outputs are valid once it is synchronised.
+ *  - Every call returns a prosper_status (0 = success).  No C++ exception
+ *    crosses the ABI.  On failure nothing has been enqueued and the text of
+ *    the error is available from prosper_last_error().
+ *  - Matrices are row-major, float32 unless stated:
+ *      Y  N x D   data, row n is y_n
+ *      W  D x H   dictionary, column h is component W_h  (f = W s)
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef PROSPER_H
+#define PROSPER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PROSPER_OK = 0,
+    PROSPER_EINVAL = -1,    /* an argument is outside its documented range      */
+    PROSPER_ENOMEM = -2,    /* device memory for the context could not be had   */
+    PROSPER_EDEVICE = -3,   /* a HIP runtime error (no GPU, launch failure, ...) */
+    PROSPER_EBUSY = -4,     /* serving queue full; nothing was queued           */
+    PROSPER_ENOTFOUND = -5, /* unknown serving request id                       */
+    PROSPER_ETIMEDOUT = -6  /* serving wait ran out of time; request still live */
+} prosper_status;
+
+typedef enum { PROSPER_BSC = 0, PROSPER_TSC = 1, PROSPER_MCA = 2 } prosper_model;
+
+/* Precision of the N x D x H projection contraction (W^T y for all latents).
+ *  PROSPER_FP32: FP32 MFMA (v_mfma_f32_16x16x4_f32), FP32 accumulation.
+ *  PROSPER_BF16: BF16 MFMA with FP32 accumulation; each operand is split into
+ *                a BF16 head and a BF16 tail and three products are summed
+ *                (head*head + head*tail + tail*head).
+ * Everything after the projection (state log-joints, normalisation, moments)
+ * runs in FP32; M-step solve and the sigma/pi reductions run in FP64. */
+typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1 } prosper_precision;
+
+/* Flags for prosper_args.flags (no flag is defined in this build; must be 0) */
+#define PROSPER_FLAG_NONE          0u
+
+/* Limits of this build */
+#define PROSPER_MAX_HPRIME   32
+#define PROSPER_MAX_D        1024
+#define PROSPER_MAX_H        1024
+#define PROSPER_MAX_TOPK     8
+#define PROSPER_MAX_STATES   (1 << 20)
+
+typedef struct {
+    int32_t model;          /* prosper_model */
+    int32_t precision;      /* prosper_precision */
+    int64_t N;              /* data points, >= 0 (0 = no-op) */
+    int32_t D, H;           /* observed / latent dimensions, 1..PROSPER_MAX_D / _H */
+    int32_t Hprime;         /* 1 <= H' <= min(H, PROSPER_MAX_HPRIME) */
+    int32_t gamma;          /* 0 <= gamma <= H'; |K| <= PROSPER_MAX_STATES */
+    double  pi;             /* prior sparsity, 0 < pi < 1 (Eq. 1) */
+    double  sigma;          /* noise standard deviation, > 0 and finite (Eq. 2) */
+    const double* theta_dev;/* optional device pointer to {pi, sigma}; when set the
+                               kernels read pi and sigma from it (no host sync in an
+                               EM loop) and the host values above are ignored */
+    int32_t topk;           /* 0..PROSPER_MAX_TOPK most probable states per point;
+                               topk <= |K| */
+    int32_t accumulate;     /* 1: add the M-step sufficient statistics into acc */
+    uint32_t flags;         /* PROSPER_FLAG_NONE */
+    int32_t reserved;
+} prosper_args;
+
+/* Per-point outputs of the E-step; any pointer may be NULL to skip it.
+ * All device pointers. */
+typedef struct {
+    int32_t*  sel;      /* N x H'   preselected latent indices I_n, ascending */
+    float*    s_mean;   /* N x H'   <s_h> under q_n, aligned with sel */
+    float*    logL;     /* N        log sum_{s in K_n} p(y_n, s | Theta)
+                                    (natural log, all constants included) */
+    uint32_t* top_mask; /* N x topk slot masks of the most probable states
+                           (bit j = slot j, i.e. latent sel[n][j], is non-zero);
+                           TSC: N x topk x 2 = {active mask, minus-sign mask} */
+    float*    top_q;    /* N x topk their posterior probabilities q_n(s),
+                           descending; equal q ordered by canonical state order */
+    uint8_t*  flagged;  /* N        1 if the H'-th and (H'+1)-th selection scores
+                                    are within 1e-6 relative (max(1,|r|)) */
+} prosper_point_out;
+
+/* Sufficient statistics for the M-step, accumulated (added) by prosper_estep
+ * when args.accumulate = 1.  The caller zeroes them before the first E-step
+ * of an iteration.  Device pointers.
+ *   BSC/TSC:  A (D x H) += y_n <s>_n^T ;  B (H x H, upper triangle incl.
+ *             diagonal in row-major h <= h') += <s s^T>_n
+ *   MCA:      A (D x H) += R_n o y_n  (numerator);  B (D x H) += R_n
+ *             (denominator), R_n[d,h] = posterior mass of the states whose max
+ *             over active components at pixel d is attained first by h and is > 0
+ *   scal (5 doubles): [0] sum_n <#nonzero(s)>  [1] sum_n logL_n
+ *             [2] sum_n ||y_n||^2  [3] sum_n <||y_n - f(s)||^2> (MCA only)
+ *             [4] N */
+typedef struct {
+    float*  A;
+    float*  B;
+    double* scal;
+} prosper_acc;
+
+typedef struct prosper_ctx prosper_ctx;
+
+/* Create a context on HIP device `device`.  `workspace_bytes` is an initial
+ * reservation (0 = grow on demand).  Returns EDEVICE when no GPU is usable. */
+prosper_status prosper_ctx_create(int device, size_t workspace_bytes, prosper_ctx** out);
+void           prosper_ctx_destroy(prosper_ctx* ctx);
+/* Text of the last failure on this context (or of the last context-less call
+ * on this thread when ctx is NULL).  Never NULL. */
+const char*    prosper_last_error(const prosper_ctx* ctx);
+
+/* Per-kernel timing ------------------------------------------------------
+ * When enabled, every kernel group the context launches (parameter prep,
+ * projection + preselection, state walk, A accumulation, M-step) is
+ * bracketed by HIP events recorded on the stream it runs on.
+ * prosper_profile(ctx, 1) enables and clears the counters, (ctx, 0) disables.
+ * prosper_profile_read waits for the recorded events, and fills up to `cap`
+ * entries: group name (static string), total elapsed ms and launch count.
+ * Returns the number of groups (may exceed cap), or a negative status. */
+prosper_status prosper_profile(prosper_ctx* ctx, int32_t enable);
+int32_t        prosper_profile_read(prosper_ctx* ctx, int32_t cap, const char** names,
+                                    double* total_ms, int64_t* launches);
+
+/* Host-only helpers (no GPU needed) ------------------------------------ */
+
+/* Validate an argument block exactly as prosper_estep does (shape, range,
+ * enum and state-count checks; pointers are not inspected). */
+prosper_status prosper_validate_args(const prosper_args* args);
+
+/* |K| for (model, H', gamma); EINVAL for out-of-range input. */
+prosper_status prosper_state_count(int32_t model, int32_t Hprime, int32_t gamma, int64_t* count);
+
+/* The canonical state table: k ascending, slot tuples lexicographically,
+ * TSC sign patterns of one support in binary counting order (bit i of the
+ * counter is the sign of the i-th active slot, 0 -> +1).  Host buffers of
+ * `capacity` entries; act[k] = active-slot mask, sgn[k] = minus-sign mask
+ * (zero for BSC/MCA; sgn may be NULL). */
+prosper_status prosper_state_table(int32_t model, int32_t Hprime, int32_t gamma,
+                                   uint32_t* act, uint32_t* sgn, int64_t capacity);
+
+/* E-step ---------------------------------------------------------------- */
+
+/* Truncated E-step over N points.
+ * Y: N x D FP32 (device), W: D x H FP32 (device).  For each point: ranking of
+ * all H latents by the singleton log-joint (ties to the lower index), the H'
+ * best as I_n, every state of K_n scored with its log-joint (Eq. 1 + Eq. 2),
+ * log-sum-exp normalisation to q_n, and the moments / statistics requested in
+ * `out` and `acc` (acc may be NULL when args.accumulate = 0).
+ * NaN in Y is not checked and propagates into logL. */
+prosper_status prosper_estep(prosper_ctx* ctx, const prosper_args* args,
+                             const float* Y, const float* W,
+                             const prosper_point_out* out, const prosper_acc* acc,
+                             void* stream);
+
+/* M-step ----------------------------------------------------------------- */
+
+/* New parameters from one E-step's statistics, in FP64 on the device.
+ *   BSC/TSC: W_new = A B^-1 on the latents with B_hh > 0 (Cholesky of that
+ *            block; other columns keep W_old), pi = scal[0]/(N H),
+ *            sigma^2 = (scal[2] - 2 tr(W_new^T A) + tr(W_new^T W_new B))/(N D)
+ *   MCA:     W_new[d,h] = A[d,h]/B[d,h] where B[d,h] > 0 (else W_old),
+ *            pi as above, sigma^2 = scal[3]/(N D)
+ * W_old and W_new (D x H FP32) may alias.  theta_new (device, 2 doubles) gets
+ * {pi, sigma}; it may equal args->theta_dev.  args supplies model, D, H. */
+prosper_status prosper_mstep(prosper_ctx* ctx, const prosper_args* args,
+                             const prosper_acc* acc, const float* W_old, float* W_new,
+                             double* theta_new, void* stream);
+
+/* Serving: E-step-only posterior inference with continuous batching ------ */
+
+typedef struct prosper_server prosper_server;
+
+/* Start a server.  It copies W (device or host pointer, D x H FP32) once and
+ * keeps it, its derived tables and the state tables resident.  Requests are
+ * admitted while the device memory they need fits in mem_budget_bytes and
+ * fewer than max_inflight are on the GPU; admitted requests run concurrently
+ * on `n_streams` HIP streams (1..8).  queue_capacity bounds pending requests. */
+prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_device,
+                             int32_t model, int32_t D, int32_t H, double pi,
+                             double sigma, int32_t precision, size_t mem_budget_bytes,
+                             int32_t max_inflight, int32_t n_streams,
+                             int32_t queue_capacity, prosper_server** out);
+
+/* Queue one request of `npatches` points (host buffer Y_host, npatches x D).
+ * The server thread reads Y_host when it admits the request, so the buffer
+ * must stay valid until prosper_serve_wait returns for this id.  The per-point
+ * outputs in out_host are host buffers with the layouts of prosper_point_out
+ * (NULL to skip) and are filled when the request completes.  Returns EBUSY
+ * when the queue is full and EINVAL for a request larger than the budget. */
+prosper_status prosper_serve_submit(prosper_server* srv, const float* Y_host, int64_t npatches,
+                                    int32_t Hprime, int32_t gamma, int32_t topk,
+                                    const prosper_point_out* out_host, uint64_t* req_id);
+
+/* Wait for a request (timeout_us < 0: forever).  On success the outputs are
+ * in place, *latency_ms (may be NULL) is submit-to-completion wall time and
+ * the id is retired.  The request's own status is returned (a failed request
+ * does not stop the server). */
+prosper_status prosper_serve_wait(prosper_server* srv, uint64_t req_id, int64_t timeout_us,
+                                  double* latency_ms);
+
+/* Drain the queue, stop the scheduler thread and free the server. */
+prosper_status prosper_serve_stop(prosper_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROSPER_H */

@@ -1,0 +1,172 @@
+"""Torch-facing wrappers of the C ABI (device memory and streams only).
+
+    ctx = Context(0)
+    out = estep(Y, W, pi, sigma, Hprime=12, gamma=4)           # BSC, FP32
+    acc = new_acc("bsc", D, H); estep(..., acc=acc)             # accumulate statistics
+    W1, theta = mstep(acc, W, model="bsc")                      # FP64 M-step on device
+
+All tensors live on the GPU; every step of the computation runs in
+libprosper.so.  Outputs are valid once the current stream is synchronised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib
+
+__all__ = ["Context", "context", "estep", "mstep", "new_acc", "zero_acc", "state_count",
+           "state_table", "ProsperError"]
+
+ProsperError = _lib.ProsperError
+state_count = _lib.state_count
+state_table = _lib.state_table
+
+
+class Context:
+    """A libprosper context bound to one HIP device (owns workspace and the
+    cached state tables)."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
+        lib = _lib.load()
+        h = C.c_void_p()
+        _lib.check(lib.prosper_ctx_create(int(device), int(workspace_bytes), C.byref(h)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().prosper_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return _lib.last_error(self.handle)
+
+
+_contexts: Dict[int, Context] = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _dev_f32(name: str, t: torch.Tensor) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major)")
+    return t
+
+
+def new_acc(model: str, D: int, H: int, device=None) -> Dict[str, torch.Tensor]:
+    """Zeroed M-step accumulators (A: D x H, B: H x H or D x H for MCA, scal: 5 doubles)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    Bshape = (D, H) if model == "mca" else (H, H)
+    return {"A": torch.zeros((D, H), dtype=torch.float32, device=dev),
+            "B": torch.zeros(Bshape, dtype=torch.float32, device=dev),
+            "scal": torch.zeros(5, dtype=torch.float64, device=dev)}
+
+
+def zero_acc(acc: Dict[str, torch.Tensor]):
+    for t in acc.values():
+        t.zero_()
+
+
+def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0, *,
+          Hprime: int, gamma: int, model: str = "bsc", precision: str = "fp32",
+          topk: int = 0, acc: Optional[Dict[str, torch.Tensor]] = None,
+          theta: Optional[torch.Tensor] = None,
+          want: Sequence[str] = ("sel", "s_mean", "logL", "flagged"),
+          out: Optional[Dict[str, torch.Tensor]] = None,
+          ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None
+          ) -> Dict[str, torch.Tensor]:
+    """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
+
+    Returns the requested per-point outputs: sel (N x H' int32), s_mean
+    (N x H'), logL (N), flagged (N uint8), top_mask / top_q (N x topk).
+    `theta` (2 doubles on the device: pi, sigma) overrides pi and sigma.
+    `out` may supply preallocated output tensors (same keys).
+    """
+    _dev_f32("Y", Y)
+    _dev_f32("W", W)
+    N, D = Y.shape
+    D2, H = W.shape
+    if D2 != D:
+        raise ValueError("Y is N x D and W must be D x H")
+    ctx = ctx or context(Y.device.index)
+    dev = Y.device
+    res: Dict[str, torch.Tensor] = {}
+    out = dict(out or {})
+
+    def get(key, shape, dtype):
+        if key in out:
+            t = out[key]
+            if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous():
+                raise ValueError(f"out[{key!r}] must be {dtype} {tuple(shape)} contiguous")
+            return t
+        return torch.empty(shape, dtype=dtype, device=dev)
+
+    if "sel" in want or "sel" in out:
+        res["sel"] = get("sel", (N, Hprime), torch.int32)
+    if "s_mean" in want or "s_mean" in out:
+        res["s_mean"] = get("s_mean", (N, Hprime), torch.float32)
+    if "logL" in want or "logL" in out:
+        res["logL"] = get("logL", (N,), torch.float32)
+    if "flagged" in want or "flagged" in out:
+        res["flagged"] = get("flagged", (N,), torch.uint8)
+    if topk:
+        mshape = (N, topk, 2) if model == "tsc" else (N, topk)
+        res["top_mask"] = get("top_mask", mshape, torch.int32)
+        res["top_q"] = get("top_q", (N, topk), torch.float32)
+    po = _lib.PointOut(_ptr(res.get("sel")), _ptr(res.get("s_mean")), _ptr(res.get("logL")),
+                       _ptr(res.get("top_mask")), _ptr(res.get("top_q")), _ptr(res.get("flagged")))
+    accs = None
+    if acc is not None:
+        accs = _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]))
+    args = _lib.make_args(model, precision, N, D, H, Hprime, gamma, pi, sigma,
+                          _ptr(theta), topk, 1 if acc is not None else 0)
+    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    lib = _lib.load()
+    _lib.check(lib.prosper_estep(ctx.handle, C.byref(args), _ptr(Y), _ptr(W), C.byref(po),
+                                 C.byref(accs) if accs is not None else None, C.c_void_p(st)),
+               ctx.handle)
+    return res
+
+
+def mstep(acc: Dict[str, torch.Tensor], W_old: torch.Tensor, *, model: str = "bsc",
+          W_new: Optional[torch.Tensor] = None, theta_new: Optional[torch.Tensor] = None,
+          ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None):
+    """FP64 M-step on the device.  Returns (W_new, theta_new) where theta_new
+    holds (pi, sigma) as two doubles on the device."""
+    _dev_f32("W_old", W_old)
+    D, H = W_old.shape
+    ctx = ctx or context(W_old.device.index)
+    if W_new is None:
+        W_new = torch.empty_like(W_old)
+    if theta_new is None:
+        theta_new = torch.empty(2, dtype=torch.float64, device=W_old.device)
+    args = _lib.make_args(model, "fp32", 0, D, H, 1, 0)
+    accs = _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]))
+    st = (stream or torch.cuda.current_stream(W_old.device)).cuda_stream
+    _lib.check(_lib.load().prosper_mstep(ctx.handle, C.byref(args), C.byref(accs), _ptr(W_old),
+                                         _ptr(W_new), _ptr(theta_new), C.c_void_p(st)),
+               ctx.handle)
+    return W_new, theta_new

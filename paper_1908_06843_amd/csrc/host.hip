@@ -1,0 +1,586 @@
+// Host side of libprosper: the C ABI of prosper.h -- argument validation,
+// the canonical state table, the context (device workspace, cached state
+// tables) and the launch sequence of one E-step / M-step.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "prosper_internal.hpp"
+
+namespace prosper {
+size_t project_lds_bytes(int Dp, int H, int prec, int tm);
+size_t states_max_lds_bytes(int Hp, int D, int64_t nstates, bool acc);
+}  // namespace prosper
+
+using namespace prosper;
+
+namespace {
+
+thread_local std::string g_tls_err;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Table {
+  uint32_t* act = nullptr;
+  uint32_t* sgn = nullptr;
+  int64_t count = 0;
+};
+
+int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+}  // namespace
+
+struct ProfEntry {
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+
+struct prosper_ctx {
+  int device = 0;
+  int num_cu = 256;
+  std::string err;
+  DevBuf prep, scratch, mwork;
+  std::map<std::tuple<int, int, int>, Table> tables;
+  // per-kernel-group timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::tuple<const char*, hipEvent_t, hipEvent_t>> ev_pending;
+  std::map<std::string, ProfEntry> prof_tab;
+  std::vector<std::string> prof_order;
+};
+
+namespace {
+
+prosper_status fail(prosper_ctx* c, prosper_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_tls_err = msg;
+  return st;
+}
+
+prosper_status hip_fail(prosper_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return fail(c, PROSPER_EDEVICE, m);
+}
+
+// grow-only device buffer; freeing waits for the device (hipFree does)
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (b.cap >= bytes) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return e;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t cap = bytes + bytes / 4 + 4096;
+  hipError_t e = hipMalloc(&b.p, cap);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.cap = cap;
+  return hipSuccess;
+}
+
+}  // namespace
+
+namespace prosper {
+// Canonical enumeration: k ascending, slot tuples lexicographic, TSC sign
+// codes counting up (bit i of the code = sign of the i-th active slot).
+void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
+                 std::vector<uint32_t>& sgn) {
+  act.clear();
+  sgn.clear();
+  const int kmax = gamma < Hp ? gamma : Hp;
+  for (int k = 0; k <= kmax; ++k) {
+    std::vector<int> c(k);
+    for (int i = 0; i < k; ++i) c[i] = i;
+    while (true) {
+      uint32_t a = 0;
+      for (int i = 0; i < k; ++i) a |= 1u << c[i];
+      if (model == PROSPER_TSC) {
+        for (uint32_t code = 0; code < (1u << k); ++code) {
+          uint32_t s = 0;
+          for (int i = 0; i < k; ++i)
+            if ((code >> i) & 1u) s |= 1u << c[i];
+          act.push_back(a);
+          sgn.push_back(s);
+        }
+      } else {
+        act.push_back(a);
+        sgn.push_back(0u);
+      }
+      // next combination in lexicographic order
+      int i = k - 1;
+      while (i >= 0 && c[i] == Hp - k + i) --i;
+      if (i < 0) break;
+      ++c[i];
+      for (int j = i + 1; j < k; ++j) c[j] = c[j - 1] + 1;
+    }
+  }
+}
+
+prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* out,
+                            std::string* msg) {
+  if (model != PROSPER_BSC && model != PROSPER_TSC && model != PROSPER_MCA) {
+    if (msg) *msg = "unknown model";
+    return PROSPER_EINVAL;
+  }
+  if (Hp < 1 || Hp > PROSPER_MAX_HPRIME) {
+    if (msg) *msg = "Hprime outside 1..32";
+    return PROSPER_EINVAL;
+  }
+  if (gamma < 0 || gamma > Hp) {
+    if (msg) *msg = "gamma outside 0..Hprime";
+    return PROSPER_EINVAL;
+  }
+  const int V1 = (model == PROSPER_TSC) ? 2 : 1;
+  double total = 0.0;
+  int64_t cnt = 0;
+  for (int k = 0; k <= gamma; ++k) {
+    const double t = (double)binom(Hp, k) * std::pow((double)V1, k);
+    total += t;
+    if (total > (double)PROSPER_MAX_STATES) {
+      if (msg) *msg = "truncated state set larger than PROSPER_MAX_STATES";
+      return PROSPER_EINVAL;
+    }
+    cnt += binom(Hp, k) * ((int64_t)1 << (V1 == 2 ? k : 0));
+  }
+  *out = cnt;
+  return PROSPER_OK;
+}
+}  // namespace prosper
+
+namespace {
+
+prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstates) {
+  if (!a) {
+    *msg = "args is NULL";
+    return PROSPER_EINVAL;
+  }
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_MCA) {
+    *msg = "unknown model";
+    return PROSPER_EINVAL;
+  }
+  if (a->precision != PROSPER_FP32 && a->precision != PROSPER_BF16) {
+    *msg = "unknown precision";
+    return PROSPER_EINVAL;
+  }
+  if (a->N < 0) {
+    *msg = "N < 0";
+    return PROSPER_EINVAL;
+  }
+  if (a->D < 1 || a->D > PROSPER_MAX_D) {
+    *msg = "D outside 1..1024";
+    return PROSPER_EINVAL;
+  }
+  if (a->H < 1 || a->H > PROSPER_MAX_H) {
+    *msg = "H outside 1..1024";
+    return PROSPER_EINVAL;
+  }
+  if (a->Hprime < 1 || a->Hprime > a->H || a->Hprime > PROSPER_MAX_HPRIME) {
+    *msg = "Hprime outside 1..min(H, 32)";
+    return PROSPER_EINVAL;
+  }
+  if (a->gamma < 0 || a->gamma > a->Hprime) {
+    *msg = "gamma outside 0..Hprime";
+    return PROSPER_EINVAL;
+  }
+  if (!a->theta_dev) {
+    if (!(a->pi > 0.0 && a->pi < 1.0)) {
+      *msg = "pi outside (0, 1)";
+      return PROSPER_EINVAL;
+    }
+    if (!(a->sigma > 0.0) || !std::isfinite(a->sigma)) {
+      *msg = "sigma must be positive and finite";
+      return PROSPER_EINVAL;
+    }
+  }
+  if (a->topk < 0 || a->topk > PROSPER_MAX_TOPK) {
+    *msg = "topk outside 0..8";
+    return PROSPER_EINVAL;
+  }
+  if (a->accumulate != 0 && a->accumulate != 1) {
+    *msg = "accumulate must be 0 or 1";
+    return PROSPER_EINVAL;
+  }
+  if (a->flags != 0u) {
+    *msg = "unknown flag bits";
+    return PROSPER_EINVAL;
+  }
+  int64_t ns = 0;
+  prosper_status st = count_states(a->model, a->Hprime, a->gamma, &ns, msg);
+  if (st != PROSPER_OK) return st;
+  if (a->topk > ns) {
+    *msg = "topk larger than the truncated state set";
+    return PROSPER_EINVAL;
+  }
+  if (a->model == PROSPER_MCA) {
+    const size_t lds = states_max_lds_bytes(a->Hprime, a->D, ns, a->accumulate != 0);
+    if (lds > 150 * 1024) {
+      *msg = "MCA shape (Hprime x D and |K|) exceeds the per-workgroup LDS of this build";
+      return PROSPER_EINVAL;
+    }
+  }
+  if (nstates) *nstates = ns;
+  return PROSPER_OK;
+}
+
+prosper_status get_table(prosper_ctx* c, int model, int Hp, int gamma, Table** out) {
+  auto key = std::make_tuple(model == PROSPER_MCA ? PROSPER_BSC : model, Hp, gamma);
+  auto it = c->tables.find(key);
+  if (it != c->tables.end()) {
+    *out = &it->second;
+    return PROSPER_OK;
+  }
+  std::vector<uint32_t> act, sgn;
+  build_table(model, Hp, gamma, act, sgn);
+  Table t;
+  t.count = (int64_t)act.size();
+  hipError_t e = hipMalloc(&t.act, act.size() * 4);
+  if (e == hipSuccess) e = hipMalloc(&t.sgn, sgn.size() * 4);
+  if (e == hipSuccess) e = hipMemcpy(t.act, act.data(), act.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(t.sgn, sgn.data(), sgn.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (t.act) hipFree(t.act);
+    if (t.sgn) hipFree(t.sgn);
+    return hip_fail(c, e, "state table upload");
+  }
+  auto ins = c->tables.emplace(key, t);
+  *out = &ins.first->second;
+  return PROSPER_OK;
+}
+
+
+
+}  // namespace
+
+namespace prosper {
+size_t prep_bytes(int Dp, int H, int prec) {
+  size_t b = 0;
+  auto add = [&](size_t n) { b = ((b + 255) & ~(size_t)255) + n; };
+  add((size_t)H * Dp * 4);
+  add(prec == PROSPER_BF16 ? (size_t)H * Dp * 2 : 0);
+  add(prec == PROSPER_BF16 ? (size_t)H * Dp * 2 : 0);
+  add((size_t)H * H * 4);
+  add((size_t)H * 4);
+  add((size_t)H * 4);
+  add(4);
+  add(sizeof(Theta));
+  return b + 256;
+}
+
+Prepared carve_prep(void* base, int Dp, int H, int prec) {
+  Carve cv{reinterpret_cast<char*>(base)};
+  Prepared p;
+  p.Pt32 = cv.take<float>((size_t)H * Dp);
+  p.Pt_hi = cv.take<bf16>(prec == PROSPER_BF16 ? (size_t)H * Dp : 0);
+  p.Pt_lo = cv.take<bf16>(prec == PROSPER_BF16 ? (size_t)H * Dp : 0);
+  p.G = cv.take<float>((size_t)H * H);
+  p.hn_hi = cv.take<float>(H);
+  p.hn_lo = cv.take<float>(H);
+  p.pnorm = cv.take<float>(1);
+  p.theta = cv.take<Theta>(1);
+  return p;
+}
+}  // namespace prosper
+
+
+namespace {
+hipEvent_t prof_event(prosper_ctx* c) {
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Runs `launch` between two events on stream s when profiling is enabled.
+template <typename F>
+hipError_t timed(prosper_ctx* c, const char* name, hipStream_t s, F&& launch) {
+  if (!c->prof) return launch();
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  hipEventRecord(a, s);
+  hipError_t e = launch();
+  hipEventRecord(b, s);
+  c->ev_pending.emplace_back(name, a, b);
+  return e;
+}
+
+void prof_collect(prosper_ctx* c) {
+  for (auto& t : c->ev_pending) {
+    hipEvent_t a = std::get<1>(t), b = std::get<2>(t);
+    hipEventSynchronize(b);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, a, b);
+    std::string name = std::get<0>(t);
+    if (!c->prof_tab.count(name)) c->prof_order.push_back(name);
+    c->prof_tab[name].ms += ms;
+    c->prof_tab[name].launches += 1;
+    c->ev_free.push_back(a);
+    c->ev_free.push_back(b);
+  }
+  c->ev_pending.clear();
+}
+}  // namespace
+
+namespace prosper {
+// Launch sequence of one E-step after the parameter preparation: projection
+// and preselection, state walk, A accumulation.  Shared by prosper_estep and
+// the serving runtime (which prepares its dictionary once).
+hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int D, int H, int Hp,
+                             int gamma, int64_t ns, const uint32_t* tab_act,
+                             const uint32_t* tab_sgn, const Prepared& p, const Scratch& sc,
+                             uint8_t* flagged, float* logL, uint32_t* top_mask, float* top_q,
+                             int topk, float* A, float* B, double* scal, int num_cu,
+                             hipStream_t s) {
+  const int Dp = round_up(D, 32);
+  hipError_t e = launch_project_select(model, prec, Y, N, D, Dp, H, Hp, p, sc, flagged, scal, s);
+  if (e != hipSuccess) return e;
+  if (model == PROSPER_MCA)
+    return launch_states_max(Hp, gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL, top_mask, top_q,
+                             topk, A, B, scal, s);
+  e = launch_states_lin(model, Hp, gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask,
+                        top_q, topk, B, scal, s);
+  if (e == hipSuccess && A) e = launch_accum_A(Y, N, D, H, Hp, sc, A, num_cu, s);
+  return e;
+}
+}  // namespace prosper
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* prosper_last_error(const prosper_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_tls_err.c_str();
+}
+
+prosper_status prosper_profile(prosper_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
+  prof_collect(c);
+  c->prof_tab.clear();
+  c->prof_order.clear();
+  c->prof = enable != 0;
+  return PROSPER_OK;
+}
+
+int32_t prosper_profile_read(prosper_ctx* c, int32_t cap, const char** names, double* total_ms,
+                             int64_t* launches) {
+  if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
+  prof_collect(c);
+  int32_t i = 0;
+  for (const std::string& n : c->prof_order) {
+    if (i < cap) {
+      // the names are string literals of this library
+      static const char* known[] = {"prep", "project_select", "states_lin", "states_max",
+                                    "accum_A", "mstep"};
+      const char* nm = "";
+      for (const char* k : known)
+        if (n == k) nm = k;
+      if (names) names[i] = nm;
+      if (total_ms) total_ms[i] = c->prof_tab[n].ms;
+      if (launches) launches[i] = c->prof_tab[n].launches;
+    }
+    ++i;
+  }
+  return i;
+}
+
+prosper_status prosper_validate_args(const prosper_args* args) {
+  std::string msg;
+  prosper_status st = validate(args, &msg, nullptr);
+  if (st != PROSPER_OK) g_tls_err = msg;
+  return st;
+}
+
+prosper_status prosper_state_count(int32_t model, int32_t Hprime, int32_t gamma, int64_t* count) {
+  std::string msg;
+  if (!count) return fail(nullptr, PROSPER_EINVAL, "count is NULL");
+  prosper_status st = count_states(model, Hprime, gamma, count, &msg);
+  if (st != PROSPER_OK) g_tls_err = msg;
+  return st;
+}
+
+prosper_status prosper_state_table(int32_t model, int32_t Hprime, int32_t gamma, uint32_t* act,
+                                   uint32_t* sgn, int64_t capacity) {
+  int64_t n = 0;
+  std::string msg;
+  prosper_status st = count_states(model, Hprime, gamma, &n, &msg);
+  if (st != PROSPER_OK) return fail(nullptr, st, msg);
+  if (!act) return fail(nullptr, PROSPER_EINVAL, "act is NULL");
+  if (capacity < n) return fail(nullptr, PROSPER_EINVAL, "capacity smaller than the state count");
+  std::vector<uint32_t> a, s;
+  build_table(model, Hprime, gamma, a, s);
+  std::memcpy(act, a.data(), a.size() * 4);
+  if (sgn) std::memcpy(sgn, s.data(), s.size() * 4);
+  return PROSPER_OK;
+}
+
+prosper_status prosper_ctx_create(int device, size_t workspace_bytes, prosper_ctx** out) {
+  if (!out) return fail(nullptr, PROSPER_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) return fail(nullptr, PROSPER_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, PROSPER_EINVAL, "device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  prosper_ctx* c = new (std::nothrow) prosper_ctx();
+  if (!c) return fail(nullptr, PROSPER_ENOMEM, "host allocation failed");
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cu = prop.multiProcessorCount;
+  if (workspace_bytes) {
+    e = ensure(c->scratch, workspace_bytes);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, PROSPER_ENOMEM, "workspace allocation failed");
+    }
+  }
+  *out = c;
+  return PROSPER_OK;
+}
+
+void prosper_ctx_destroy(prosper_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto& kv : c->tables) {
+    hipFree(kv.second.act);
+    hipFree(kv.second.sgn);
+  }
+  if (c->prep.p) hipFree(c->prep.p);
+  if (c->scratch.p) hipFree(c->scratch.p);
+  if (c->mwork.p) hipFree(c->mwork.p);
+  prof_collect(c);
+  for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
+  delete c;
+}
+
+prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float* Y,
+                             const float* W, const prosper_point_out* out,
+                             const prosper_acc* acc, void* stream) {
+  if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
+  std::string msg;
+  int64_t ns = 0;
+  prosper_status st = validate(a, &msg, &ns);
+  if (st != PROSPER_OK) return fail(c, st, msg);
+  if (a->N == 0) return PROSPER_OK;
+  if (!Y || !W) return fail(c, PROSPER_EINVAL, "Y or W is NULL");
+  if (a->accumulate && (!acc || !acc->A || !acc->B || !acc->scal))
+    return fail(c, PROSPER_EINVAL, "accumulate=1 needs acc->A, acc->B and acc->scal");
+  if (a->topk > 0 && out && !out->top_mask && !out->top_q)
+    return fail(c, PROSPER_EINVAL, "topk > 0 needs top_mask or top_q");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+
+  const int model = a->model, prec = a->precision;
+  const int64_t N = a->N;
+  const int D = a->D, H = a->H, Hp = a->Hprime;
+  const int Dp = round_up(D, 32);
+
+  Table* tab = nullptr;
+  st = get_table(c, model, Hp, a->gamma, &tab);
+  if (st != PROSPER_OK) return st;
+
+  e = ensure(c->prep, prep_bytes(Dp, H, prec));
+  if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "workspace (parameters) allocation failed");
+  Prepared p = carve_prep(c->prep.p, Dp, H, prec);
+
+  const bool need_sel = !(out && out->sel);
+  const bool need_sm = !(out && out->s_mean);
+  size_t sb = 0;
+  auto add = [&](size_t n) { sb = ((sb + 255) & ~(size_t)255) + n; };
+  add(need_sel ? (size_t)N * Hp * 4 : 0);
+  add((size_t)N * Hp * 4);
+  add((size_t)N * 4);
+  add(need_sm ? (size_t)N * Hp * 4 : 0);
+  add((size_t)N * 4);
+  add(4);
+  e = ensure(c->scratch, sb + 256);
+  if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "workspace (per point) allocation failed");
+  Carve cv{reinterpret_cast<char*>(c->scratch.p)};
+  Scratch sc;
+  int32_t* sel_ws = cv.take<int32_t>(need_sel ? (size_t)N * Hp : 0);
+  sc.bc = cv.take<float>((size_t)N * Hp);
+  sc.yy = cv.take<float>((size_t)N);
+  float* sm_ws = cv.take<float>(need_sm ? (size_t)N * Hp : 0);
+  sc.redo_list = cv.take<int32_t>((size_t)N);
+  sc.redo_count = cv.take<int32_t>(1);
+  sc.sel = need_sel ? sel_ws : out->sel;
+  sc.s_mean = need_sm ? sm_ws : out->s_mean;
+
+  uint8_t* flagged = out ? out->flagged : nullptr;
+  float* logL = out ? out->logL : nullptr;
+  uint32_t* top_mask = out ? out->top_mask : nullptr;
+  float* top_q = out ? out->top_q : nullptr;
+
+  const int Dp2 = Dp;
+  e = timed(c, "prep", s, [&] {
+    hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
+                                      sc.redo_count, s);
+    return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp2, p, s) : e2;
+  });
+  float* Aacc = a->accumulate ? acc->A : nullptr;
+  float* Bacc = a->accumulate ? acc->B : nullptr;
+  double* scal = a->accumulate ? acc->scal : nullptr;
+  if (e == hipSuccess)
+    e = timed(c, "project_select", s, [&] {
+      return launch_project_select(model, prec, Y, N, D, Dp2, H, Hp, p, sc, flagged, scal, s);
+    });
+  if (e == hipSuccess)
+    e = timed(c, model == PROSPER_MCA ? "states_max" : "states_lin", s, [&] {
+      if (model == PROSPER_MCA)
+        return launch_states_max(Hp, a->gamma, N, D, Dp2, H, ns, tab->act, Y, p, sc, logL,
+                                 top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
+      return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab->act, tab->sgn, p, sc, logL,
+                               top_mask, top_q, a->topk, Bacc, scal, s);
+    });
+  if (e == hipSuccess && Aacc && model != PROSPER_MCA)
+    e = timed(c, "accum_A", s, [&] { return launch_accum_A(Y, N, D, H, Hp, sc, Aacc, c->num_cu, s); });
+  if (e != hipSuccess) return hip_fail(c, e, "E-step launch");
+  return PROSPER_OK;
+}
+
+prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prosper_acc* acc,
+                             const float* W_old, float* W_new, double* theta_new, void* stream) {
+  if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
+  if (!a) return fail(c, PROSPER_EINVAL, "args is NULL");
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_MCA)
+    return fail(c, PROSPER_EINVAL, "unknown model");
+  if (a->D < 1 || a->D > PROSPER_MAX_D || a->H < 1 || a->H > PROSPER_MAX_H)
+    return fail(c, PROSPER_EINVAL, "D or H out of range");
+  if (!acc || !acc->A || !acc->B || !acc->scal || !W_old || !W_new || !theta_new)
+    return fail(c, PROSPER_EINVAL, "NULL pointer argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  e = ensure(c->mwork, mstep_workspace_bytes(a->model, a->D, a->H));
+  if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "M-step workspace allocation failed");
+  e = timed(c, "mstep", s, [&] {
+    return launch_mstep(a->model, a->D, a->H, acc->A, acc->B, acc->scal, W_old, W_new, theta_new,
+                        c->mwork.p, s);
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "M-step launch");
+  return PROSPER_OK;
+}
+
+}  // extern "C"

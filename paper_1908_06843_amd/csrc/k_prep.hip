@@ -1,0 +1,137 @@
+// Per-call parameter preparation (row a1 of the hot path): derived constants
+// of (pi, sigma), the transposed projection matrix in FP32 and as a BF16
+// head/tail pair, the Gram matrix G = W^T W and the half squared norms of
+// the projection rows.  All reductions are accumulated in FP64 and rounded
+// once, so the FP32 state walk starts from correctly rounded G and norms.
+#include <cmath>
+
+#include "prosper_internal.hpp"
+
+namespace prosper {
+
+// pi, sigma from the host values or from device memory (written by the
+// M-step); also clears the running max of the projection-row norms and the
+// redo-list counter of the unrolled state walk.
+__global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
+                        const double* __restrict__ theta_dev, Theta* __restrict__ th,
+                        float* __restrict__ pnorm, int32_t* __restrict__ redo_count) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double pi = theta_dev ? theta_dev[0] : pi_h;
+  double sigma = theta_dev ? theta_dev[1] : sigma_h;
+  const double LOG2E = 1.4426950408889634;
+  Theta t;
+  t.pi = pi;
+  t.sigma = sigma;
+  t.c0 = (double)H * log1p(-pi) - 0.5 * (double)D * log(2.0 * M_PI * sigma * sigma);
+  double lam = 1.0 / (2.0 * sigma * sigma);
+  t.lam = (float)lam;
+  t.lam2 = (float)(lam * LOG2E);
+  double c1 = (model == PROSPER_TSC) ? log(pi / (2.0 * (1.0 - pi))) : log(pi / (1.0 - pi));
+  t.c1_2 = (float)(c1 * LOG2E);
+  t.ln2 = (float)0.6931471805599453;
+  *th = t;
+  *pnorm = 0.0f;
+  if (redo_count) *redo_count = 0;
+}
+
+// Pt32[h][d] = P[d][h] (zero for d >= D), P = W or max(W, 0) (MCA, H > 1);
+// optional BF16 head/tail split.  32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, int D, int H,
+                                                   int Dp, int relu, float* __restrict__ Pt32,
+                                                   bf16* __restrict__ Pt_hi,
+                                                   bf16* __restrict__ Pt_lo) {
+  __shared__ float tile[32][33];
+  const int d0 = blockIdx.x * 32, h0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int d = d0 + r, h = h0 + tx;
+    float v = 0.0f;
+    if (d < D && h < H) {
+      v = W[(int64_t)d * H + h];
+      if (relu) v = fmaxf(v, 0.0f);
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int h = h0 + r, d = d0 + tx;
+    if (h < H && d < Dp) {
+      float v = tile[tx][r];
+      int64_t o = (int64_t)h * Dp + d;
+      Pt32[o] = v;
+      if (Pt_hi) {
+        bf16 hi = (bf16)v;
+        Pt_hi[o] = hi;
+        Pt_lo[o] = (bf16)(v - (float)hi);
+      }
+    }
+  }
+}
+
+// G[i][j] = sum_d W[d][i] W[d][j], FP64 accumulation, 16 x 16 output tiles.
+__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D, int H,
+                                              float* __restrict__ G) {
+  __shared__ double a[16][17], b[16][17];
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc = 0.0;
+  for (int d0 = 0; d0 < D; d0 += 16) {
+    int d = d0 + ty;
+    a[ty][tx] = (d < D && i0 + tx < H) ? (double)W[(int64_t)d * H + i0 + tx] : 0.0;
+    b[ty][tx] = (d < D && j0 + tx < H) ? (double)W[(int64_t)d * H + j0 + tx] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = fma(a[k][ty], b[k][tx], acc);
+    __syncthreads();
+  }
+  if (i0 + ty < H && j0 + tx < H) G[(int64_t)(i0 + ty) * H + j0 + tx] = (float)acc;
+}
+
+// hn[h] = 1/2 ||P_h||^2 in FP64 split into an FP32 head and tail; running
+// max of ||P_h||_2 (positive floats order like their bit patterns).
+__global__ __launch_bounds__(64) void k_norms(const float* __restrict__ W, int D, int H, int relu,
+                                              float* __restrict__ hn_hi, float* __restrict__ hn_lo,
+                                              float* __restrict__ pnorm) {
+  int h = blockIdx.x * 64 + threadIdx.x;
+  if (h >= H) return;
+  double acc = 0.0;
+  for (int d = 0; d < D; ++d) {
+    double v = W[(int64_t)d * H + h];
+    if (relu) v = v > 0.0 ? v : 0.0;
+    acc = fma(v, v, acc);
+  }
+  double half = 0.5 * acc;
+  float hi = (float)half;
+  hn_hi[h] = hi;
+  hn_lo[h] = (float)(half - (double)hi);
+  float nrm = (float)sqrt(acc);
+  atomicMax(reinterpret_cast<unsigned int*>(pnorm), __float_as_uint(nrm));
+}
+
+hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
+                       const Prepared& p, hipStream_t st) {
+  const int relu = (model == PROSPER_MCA && H > 1) ? 1 : 0;
+  dim3 gt((Dp + 31) / 32, (H + 31) / 32);
+  hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, st, W, D, H, Dp, relu, p.Pt32,
+                     prec == PROSPER_BF16 ? p.Pt_hi : nullptr,
+                     prec == PROSPER_BF16 ? p.Pt_lo : nullptr);
+  if (model != PROSPER_MCA) {
+    dim3 gg((H + 15) / 16, (H + 15) / 16);
+    hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G);
+  }
+  hipLaunchKernelGGL(k_norms, dim3((H + 63) / 64), dim3(64), 0, st, W, D, H, relu, p.hn_hi,
+                     p.hn_lo, p.pnorm);
+  return hipGetLastError();
+}
+
+// Separate entry so that the theta kernel (which also clears pnorm) runs
+// before k_norms on the same stream.
+hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
+                             const double* theta_dev, const Prepared& p, int32_t* redo_count,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_theta, dim3(1), dim3(64), 0, st, model, D, H, pi, sigma, theta_dev,
+                     p.theta, p.pnorm, redo_count);
+  return hipGetLastError();
+}
+
+}  // namespace prosper

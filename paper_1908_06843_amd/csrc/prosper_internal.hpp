@@ -1,0 +1,122 @@
+// Internal interfaces of libprosper: device constants, workspace layout and
+// the host-side launchers of every kernel.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "prosper.h"
+
+namespace prosper {
+
+typedef __bf16 bf16;
+
+// Derived constants of (pi, sigma) for one E-step call, computed on the
+// device (so pi and sigma may themselves live on the device, as written by
+// the M-step).  Log-joints inside the state walk are kept relative to the
+// all-zero state and in log2 units:
+//   lj(s) - lj(0) = k(s) c1 + lam (2 s^T b - s^T G s)            (BSC, TSC)
+//   lj(s) - lj(0) = k(s) c1 - lam (||y - f(s)||^2 - ||y||^2)      (MCA)
+//   lj(0)         = c0 - lam ||y||^2
+// with c1 = log(pi/(1-pi)) (BSC, MCA) or log(pi/(2(1-pi))) (TSC),
+// lam = 1/(2 sigma^2) and c0 = H log(1-pi) - D/2 log(2 pi sigma^2)
+// (Eq. 1 prior, Eq. 2 Gaussian noise).
+struct Theta {
+  double pi, sigma;
+  double c0;     // natural log
+  float lam;     // 1/(2 sigma^2)
+  float lam2;    // lam * log2(e)
+  float c1_2;    // c1 * log2(e)
+  float ln2;     // log(2)
+};
+
+// Per-(model, W) derived data, rebuilt by k_prep for every E-step call.
+struct Prepared {
+  float* Pt32;      // H x Dp   projection rows: W^T (BSC/TSC) or max(W,0)^T (MCA), zero pad
+  bf16* Pt_hi;      // H x Dp   BF16 head of Pt32 (BF16 precision only)
+  bf16* Pt_lo;      // H x Dp   BF16 tail: Pt32 - Pt_hi rounded to BF16
+  float* G;         // H x H    W^T W (BSC/TSC), FP64-accumulated then rounded
+  float* hn_hi;     // H        1/2 ||P_h||^2 as an FP32 head ...
+  float* hn_lo;     // H        ... and tail (FP64-accumulated)
+  float* pnorm;     // 1        max_h ||P_h||_2
+  Theta* theta;     // 1
+};
+
+// Per-call intermediates (device).
+struct Scratch {
+  int32_t* sel;     // N x H'
+  float* bc;        // N x H'   candidate projections b_{I_n(j)} (signed)
+  float* yy;        // N        ||y_n||^2 (FP32)
+  float* s_mean;    // N x H'
+  int32_t* redo_list;   // N   points the unrolled walk hands to the exact kernel
+  int32_t* redo_count;  // 1   (cleared by the parameter kernel of each call)
+};
+
+__host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Bump allocator over one device allocation (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// Host-side helpers shared by the ABI and the serving runtime.
+void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
+                 std::vector<uint32_t>& sgn);
+prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* out,
+                            std::string* msg);
+size_t prep_bytes(int Dp, int H, int prec);
+Prepared carve_prep(void* base, int Dp, int H, int prec);
+
+// Launchers (each returns the first HIP error it sees).
+hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
+                             const double* theta_dev, const Prepared& p, int32_t* redo_count,
+                             hipStream_t st);
+hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
+                       const Prepared& p, hipStream_t st);
+hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N, int D, int Dp,
+                                 int H, int Hp, const Prepared& p, const Scratch& s,
+                                 uint8_t* flagged, double* scal, hipStream_t st);
+// BSC / TSC state walk.  tab_act/tab_sgn: canonical state table on the device.
+hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int64_t nstates,
+                             const uint32_t* tab_act, const uint32_t* tab_sgn,
+                             const Prepared& p, const Scratch& s, float* logL,
+                             uint32_t* top_mask, float* top_q, int topk,
+                             float* B_acc, double* scal, hipStream_t st);
+// MCA state walk (max superposition).
+hipError_t launch_states_max(int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
+                             const uint32_t* tab_act, const float* Y, const Prepared& p,
+                             const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
+                             int topk, float* A_num, float* B_den, double* scal,
+                             hipStream_t st);
+// A += y <s>^T on the candidate columns.
+hipError_t launch_accum_A(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
+                          float* A, int num_cu, hipStream_t st);
+// M-step.
+size_t mstep_workspace_bytes(int model, int D, int H);
+hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
+                        const double* scal, const float* W_old, float* W_new,
+                        double* theta_new, void* work, hipStream_t st);
+
+// Projection/preselection + state walk + A accumulation (after k_prep).
+hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int D, int H, int Hp,
+                             int gamma, int64_t ns, const uint32_t* tab_act,
+                             const uint32_t* tab_sgn, const Prepared& p, const Scratch& sc,
+                             uint8_t* flagged, float* logL, uint32_t* top_mask, float* top_q,
+                             int topk, float* A, float* B, double* scal, int num_cu,
+                             hipStream_t s);
+
+// Whether a compile-time specialised state walk exists for this shape.
+bool has_tree_kernel(int model, int Hp, int gamma);
+
+}  // namespace prosper

@@ -1,0 +1,117 @@
+"""GPU parity of the sufficient statistics, the FP64 M-step and whole EM
+iterations against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import prosper_oracle as O
+from tests._common import gpu_estep, problem
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("name,N,Hp,gamma", [("bsc256", 1037, 12, 4), ("tsc", 517, 8, 3),
+                                             ("mca", 203, 10, 3), ("bars", 300, 10, 10),
+                                             ("bsc256", 300, 6, 2)])
+def test_accumulators_match_oracle(name, N, Hp, gamma):
+    Y, W, pi, sigma, wl = problem(name, N, "init")
+    g = gpu_estep(wl.model, "fp32", Y, W, pi, sigma, Hp, gamma, accumulate=True)
+    r = O.estep(wl.model, Y, W, pi, sigma, Hp, gamma)
+    B = g["B"]
+    if wl.model != "mca":   # the GPU accumulates the upper triangle of B
+        B = np.triu(B) + np.triu(B, 1).T
+    print(f"[acc] {name}: A {rel(g['A'], r['A']):.2e} B {rel(B, r['B']):.2e} "
+          f"scal {np.abs(g['scal'] - r['scal']) / np.maximum(np.abs(r['scal']), 1)}", flush=True)
+    assert rel(g["A"], r["A"]) < 2e-5
+    assert rel(B, r["B"]) < 2e-5
+    s = r["scal"]
+    assert g["scal"][0] == pytest.approx(s[0], rel=1e-5)
+    assert g["scal"][1] == pytest.approx(s[1], rel=1e-5)
+    assert g["scal"][2] == pytest.approx(s[2], rel=1e-9)
+    if wl.model == "mca":
+        assert g["scal"][3] == pytest.approx(s[3], rel=1e-5)
+    assert g["scal"][4] == N
+
+
+@pytest.mark.parametrize("model,name,N,Hp,gamma", [("bsc", "bsc256", 600, 12, 4),
+                                                   ("tsc", "tsc", 400, 8, 3),
+                                                   ("mca", "mca", 150, 10, 3),
+                                                   ("bsc", "bars", 300, 10, 10)])
+def test_mstep_matches_oracle(model, name, N, Hp, gamma):
+    """The device M-step applied to the oracle's statistics reproduces the
+    oracle's parameter update (W = A B^-1 or A / B; pi; sigma)."""
+    import torch
+    from paper_1908_06843_amd import api
+    Y, W, pi, sigma, wl = problem(name, N, "init")
+    r = O.estep(model, Y, W, pi, sigma, Hp, gamma, keep_posterior=(model != "mca"))
+    Wr, pir, sr = O.mstep(model, Y, W, r)
+    dev = torch.device("cuda", 0)
+    acc = {"A": torch.tensor(r["A"], dtype=torch.float32, device=dev),
+           "B": torch.tensor(np.triu(r["B"]) if model != "mca" else r["B"], dtype=torch.float32,
+                             device=dev),
+           "scal": torch.tensor(r["scal"], dtype=torch.float64, device=dev)}
+    Wd = torch.tensor(W, device=dev)
+    Wn, th = api.mstep(acc, Wd, model=model)
+    torch.cuda.synchronize()
+    Wn, th = Wn.cpu().numpy(), th.cpu().numpy()
+    print(f"[mstep] {model}: W {rel(Wn, Wr):.2e} pi {th[0]} vs {pir} sigma {th[1]} vs {sr}",
+          flush=True)
+    assert rel(Wn, Wr) < 1e-4
+    assert th[0] == pytest.approx(pir, rel=1e-9)
+    assert th[1] == pytest.approx(sr, rel=1e-5)
+
+
+def test_mstep_in_place_and_inactive_columns():
+    """W_new may alias W_old; latents never preselected keep their column."""
+    import torch
+    from paper_1908_06843_amd import api
+    g = np.random.default_rng(3)
+    Y = g.standard_normal((60, 5)).astype(np.float32)
+    W = g.standard_normal((5, 6)).astype(np.float32)
+    W[:, 4] = 50.0
+    r = O.estep("bsc", Y, W, 0.2, 1.0, 2, 2, keep_posterior=True)
+    Wr, _, _ = O.mstep("bsc", Y, W, r)
+    dev = torch.device("cuda", 0)
+    acc = {"A": torch.tensor(r["A"], dtype=torch.float32, device=dev),
+           "B": torch.tensor(np.triu(r["B"]), dtype=torch.float32, device=dev),
+           "scal": torch.tensor(r["scal"], dtype=torch.float64, device=dev)}
+    Wd = torch.tensor(W, device=dev)
+    api.mstep(acc, Wd, model="bsc", W_new=Wd)
+    torch.cuda.synchronize()
+    Wn = Wd.cpu().numpy()
+    np.testing.assert_array_equal(Wn[:, 4], W[:, 4])
+    assert rel(Wn, Wr) < 1e-4
+
+
+def test_em_bars_trajectory_and_monotone_free_energy():
+    """Ten exact EM iterations on bars, all on the GPU (parameters stay on the
+    device), against the oracle's trajectory; the free energy rises."""
+    import torch
+    from paper_1908_06843_amd import api
+    Y, _, _, wl = synth.make_workload("bars", N=300)
+    W0, pi0, s0 = synth.initial_params(wl, Y)
+    F_ref, W_ref, pi_ref, s_ref = O.em_run("bsc", Y, W0, pi0, s0, 10, 10, 10)
+    dev = torch.device("cuda", 0)
+    Yd = torch.tensor(Y, device=dev)
+    Wd = torch.tensor(W0, device=dev)
+    theta = torch.tensor([pi0, s0], dtype=torch.float64, device=dev)
+    acc = api.new_acc("bsc", 25, 10)
+    F = []
+    for it in range(10):
+        api.zero_acc(acc)
+        api.estep(Yd, Wd, Hprime=10, gamma=10, theta=theta, acc=acc, want=())
+        F.append(float(acc["scal"][1].item()))
+        api.mstep(acc, Wd, model="bsc", W_new=Wd, theta_new=theta)
+    torch.cuda.synchronize()
+    F = np.array(F)
+    print(f"[em] F gpu {F}\n[em] F ref {np.array(F_ref)}", flush=True)
+    np.testing.assert_allclose(F, F_ref, rtol=1e-4)
+    assert np.all(np.diff(F) >= -1e-6 * np.abs(F[:-1]))
+    th = theta.cpu().numpy()
+    assert th[0] == pytest.approx(pi_ref, rel=1e-3)
+    assert th[1] == pytest.approx(s_ref, rel=1e-3)
+    assert rel(Wd.cpu().numpy(), W_ref) < 1e-3
