@@ -356,9 +356,10 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
   if (model == PROSPER_MCA)
     return launch_states_max(Hp, gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL, top_mask, top_q,
                              topk, A, B, scal, s);
+  int tree_blocks = 0;
   e = launch_states_lin(model, Hp, gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask,
-                        top_q, topk, B, scal, s);
-  if (e == hipSuccess && A) e = launch_accum_A(Y, N, D, H, Hp, sc, A, num_cu, s);
+                        top_q, topk, A != nullptr, B, scal, num_cu, &tree_blocks, s);
+  if (e == hipSuccess && A) e = launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, A, B, s);
   return e;
 }
 }  // namespace prosper
@@ -389,7 +390,7 @@ int32_t prosper_profile_read(prosper_ctx* c, int32_t cap, const char** names, do
     if (i < cap) {
       // the names are string literals of this library
       static const char* known[] = {"prep", "project_select", "states_lin", "states_max",
-                                    "accum_A", "mstep"};
+                                    "stats", "mstep"};
       const char* nm = "";
       for (const char* k : known)
         if (n == k) nm = k;
@@ -515,6 +516,16 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   add(need_sm ? (size_t)N * Hp * 4 : 0);
   add((size_t)N * 4);
   add(4);
+  const bool lin_acc = a->accumulate && model != PROSPER_MCA;
+  const size_t npairs = (size_t)Hp * (Hp + 1) / 2;
+  StatsPlan plan = stats_plan(N, D, H, c->num_cu);
+  const bool tree_acc = lin_acc && a->topk == 0 && has_tree_kernel(model, Hp, a->gamma) &&
+                        (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
+  const size_t partB_floats =
+      tree_acc ? (size_t)c->num_cu * stats_bslice_floats() : plan.partB_floats;
+  add(lin_acc && !tree_acc ? npairs * N * 4 : 0);
+  add(lin_acc ? plan.partA_floats * 4 : 0);
+  add(lin_acc ? partB_floats * 4 : 0);
   e = ensure(c->scratch, sb + 256);
   if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "workspace (per point) allocation failed");
   Carve cv{reinterpret_cast<char*>(c->scratch.p)};
@@ -525,6 +536,11 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   float* sm_ws = cv.take<float>(need_sm ? (size_t)N * Hp : 0);
   sc.redo_list = cv.take<int32_t>((size_t)N);
   sc.redo_count = cv.take<int32_t>(1);
+  sc.ss = cv.take<float>(lin_acc && !tree_acc ? npairs * N : 0);
+  if (!(lin_acc && !tree_acc)) sc.ss = nullptr;
+  sc.partA = cv.take<float>(lin_acc ? plan.partA_floats : 0);
+  sc.partB = cv.take<float>(lin_acc ? partB_floats : 0);
+  sc.plan = plan;
   sc.sel = need_sel ? sel_ws : out->sel;
   sc.s_mean = need_sm ? sm_ws : out->s_mean;
 
@@ -540,6 +556,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
     return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp2, p, s) : e2;
   });
   float* Aacc = a->accumulate ? acc->A : nullptr;
+  int tree_blocks = 0;
   float* Bacc = a->accumulate ? acc->B : nullptr;
   double* scal = a->accumulate ? acc->scal : nullptr;
   if (e == hipSuccess)
@@ -552,10 +569,13 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
         return launch_states_max(Hp, a->gamma, N, D, Dp2, H, ns, tab->act, Y, p, sc, logL,
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
       return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab->act, tab->sgn, p, sc, logL,
-                               top_mask, top_q, a->topk, Bacc, scal, s);
+                               top_mask, top_q, a->topk, Aacc != nullptr, Bacc, scal, c->num_cu,
+                               &tree_blocks, s);
     });
   if (e == hipSuccess && Aacc && model != PROSPER_MCA)
-    e = timed(c, "accum_A", s, [&] { return launch_accum_A(Y, N, D, H, Hp, sc, Aacc, c->num_cu, s); });
+    e = timed(c, "stats", s, [&] {
+      return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s);
+    });
   if (e != hipSuccess) return hip_fail(c, e, "E-step launch");
   return PROSPER_OK;
 }

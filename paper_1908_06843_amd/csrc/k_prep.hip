@@ -5,6 +5,7 @@
 // once, so the FP32 state walk starts from correctly rounded G and norms.
 #include <cmath>
 
+#include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
 namespace prosper {
@@ -88,24 +89,26 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D
 }
 
 // hn[h] = 1/2 ||P_h||^2 in FP64 split into an FP32 head and tail; running
-// max of ||P_h||_2 (positive floats order like their bit patterns).
-__global__ __launch_bounds__(64) void k_norms(const float* __restrict__ W, int D, int H, int relu,
-                                              float* __restrict__ hn_hi, float* __restrict__ hn_lo,
-                                              float* __restrict__ pnorm) {
-  int h = blockIdx.x * 64 + threadIdx.x;
+// max of ||P_h||_2 (positive floats order like their bit patterns).  One
+// wave per latent, lanes over pixels of the transposed (contiguous) row.
+__global__ __launch_bounds__(256) void k_norms(const float* __restrict__ Pt32, int Dp, int H,
+                                               float* __restrict__ hn_hi, float* __restrict__ hn_lo,
+                                               float* __restrict__ pnorm) {
+  const int h = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (h >= H) return;
   double acc = 0.0;
-  for (int d = 0; d < D; ++d) {
-    double v = W[(int64_t)d * H + h];
-    if (relu) v = v > 0.0 ? v : 0.0;
+  for (int d = lane; d < Dp; d += 64) {
+    const double v = Pt32[(int64_t)h * Dp + d];
     acc = fma(v, v, acc);
   }
-  double half = 0.5 * acc;
-  float hi = (float)half;
-  hn_hi[h] = hi;
-  hn_lo[h] = (float)(half - (double)hi);
-  float nrm = (float)sqrt(acc);
-  atomicMax(reinterpret_cast<unsigned int*>(pnorm), __float_as_uint(nrm));
+  acc = wave_sum_d(acc);
+  if (lane == 0) {
+    const double half = 0.5 * acc;
+    const float hi = (float)half;
+    hn_hi[h] = hi;
+    hn_lo[h] = (float)(half - (double)hi);
+    atomicMax(reinterpret_cast<unsigned int*>(pnorm), __float_as_uint((float)sqrt(acc)));
+  }
 }
 
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
@@ -119,8 +122,8 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
     dim3 gg((H + 15) / 16, (H + 15) / 16);
     hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G);
   }
-  hipLaunchKernelGGL(k_norms, dim3((H + 63) / 64), dim3(64), 0, st, W, D, H, relu, p.hn_hi,
-                     p.hn_lo, p.pnorm);
+  hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi, p.hn_lo,
+                     p.pnorm);
   return hipGetLastError();
 }
 

@@ -36,12 +36,13 @@ __global__ __launch_bounds__(256) void k_states_generic(
     const uint32_t* __restrict__ tab_act, const uint32_t* __restrict__ tab_sgn,
     const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
     uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk,
-    float* __restrict__ B_acc, double* __restrict__ scal, const int32_t* __restrict__ list,
-    const int32_t* __restrict__ list_count) {
+    float* __restrict__ ss_out, float* __restrict__ B_atomic, double* __restrict__ scal,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count) {
   __shared__ GenLds sh[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   GenLds& S = sh[wave];
   const float lam2 = th->lam2, c1 = th->c1_2;
+  const int64_t Ntot = N;  // leading dimension of ss_out
   double acc_k = 0.0, acc_l = 0.0;
   // list mode: only the points named in list[0 .. *list_count)
   const int64_t npts = list ? (int64_t)*list_count : N;
@@ -166,17 +167,27 @@ __global__ __launch_bounds__(256) void k_states_generic(
         const float k2 = TSC ? S.K2[j] : S.M[j];
         kpart += k2;
         s_mean[n * Hp + j] = S.M[j] * invZ;
-        if (B_acc) {
+        if (ss_out) ss_out[(int64_t)j * Ntot + n] = k2 * invZ;
+        if (B_atomic) {
           const int sj = sel[n * Hp + j];
-          atomicAdd(&B_acc[(int64_t)sj * H + sj], k2 * invZ);
+          atomicAdd(&B_atomic[(int64_t)sj * H + sj], k2 * invZ);
         }
       }
-      if (B_acc) {
+      if (B_atomic) {  // few points (the exact kernel's redo list): direct adds
         for (int idx = lane; idx < Hp * Hp; idx += 64) {
           const int i = idx / Hp, j = idx % Hp;
           if (i < j)
-            atomicAdd(&B_acc[(int64_t)sel[n * Hp + i] * H + sel[n * Hp + j]],
+            atomicAdd(&B_atomic[(int64_t)sel[n * Hp + i] * H + sel[n * Hp + j]],
                       S.P[i * 32 + j] * invZ);
+        }
+      }
+      if (ss_out) {  // pairs i < j in row-major order after the diagonal
+        for (int idx = lane; idx < Hp * Hp; idx += 64) {
+          const int i = idx / Hp, j = idx % Hp;
+          if (i < j) {
+            const int p = Hp + i * (2 * Hp - i - 1) / 2 + (j - i - 1);
+            ss_out[(int64_t)p * Ntot + n] = S.P[i * 32 + j] * invZ;
+          }
         }
       }
       const float kmean = wave_sum(kpart) * invZ;
@@ -236,9 +247,10 @@ __global__ __launch_bounds__(256) void k_states_generic(
   X(false, 12, 5)              \
   X(true, 8, 3)
 
-#define X(T, HP, GM)                                                                     \
-  hipError_t launch_tree_##T##_##HP##_##GM(const Prepared&, const Scratch&, int64_t, int, \
-                                           float*, float*, double*, hipStream_t);
+#define X(T, HP, GM)                                                                      \
+  hipError_t launch_tree_##T##_##HP##_##GM(const Prepared&, const Scratch&, int64_t, int,  \
+                                           float*, float*, double*, int, float*, int64_t, \
+                                           hipStream_t);
 PROSPER_TREE_SHAPES(X)
 #undef X
 
@@ -253,40 +265,58 @@ bool has_tree_kernel(int model, int Hp, int gamma) {
 hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int64_t nstates,
                              const uint32_t* tab_act, const uint32_t* tab_sgn,
                              const Prepared& p, const Scratch& s, float* logL,
-                             uint32_t* top_mask, float* top_q, int topk, float* B_acc,
-                             double* scal, hipStream_t st) {
+                             uint32_t* top_mask, float* top_q, int topk, bool acc,
+                             float* acc_B, double* scal, int num_cu, int* tree_blocks,
+                             hipStream_t st) {
+  if (tree_blocks) *tree_blocks = 0;
   if (N <= 0) return hipSuccess;
   const bool tsc = (model == PROSPER_TSC);
   if (topk == 0 && has_tree_kernel(model, Hp, gamma)) {
+    // training: B partials inside the walk when B's packed triangle fits in LDS
+    int nblk = 0;
+    if (acc && (int64_t)H * (H + 1) / 2 <= stats_bslice_floats()) {
+      int64_t want = (N + 511) / 512;
+      nblk = (int)(want < num_cu ? want : num_cu);
+      if (tree_blocks) *tree_blocks = nblk;
+    }
+    float* ss_out = (acc && nblk == 0) ? s.ss : nullptr;
     hipError_t e = hipErrorInvalidValue;
-#define X(T, HP, GM) \
-  if (tsc == T && Hp == HP && gamma == GM) e = launch_tree_##T##_##HP##_##GM(p, s, N, H, logL, B_acc, scal, st);
+#define X(T, HP, GM)                                                                           \
+  if (tsc == T && Hp == HP && gamma == GM)                                                     \
+    e = launch_tree_##T##_##HP##_##GM(p, s, N, H, logL, ss_out, scal, nblk, s.partB,           \
+                                      (int64_t)stats_bslice_floats(), st);
     PROSPER_TREE_SHAPES(X)
 #undef X
     if (e != hipSuccess) return e;
     // points whose weights could overflow with the cheap pivot: exact kernel
     if (gamma > 2) {
+      float* Bat = acc ? acc_B : nullptr;
       if (tsc)
-        hipLaunchKernelGGL(k_states_generic<true>, dim3(256), dim3(256), 0, st, s.sel, s.bc, s.yy,
+        hipLaunchKernelGGL(k_states_generic<true>, dim3(32), dim3(256), 0, st, s.sel, s.bc, s.yy,
                            p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean, logL,
-                           top_mask, top_q, 0, B_acc, scal, s.redo_list, s.redo_count);
+                           top_mask, top_q, 0, (float*)nullptr, Bat, scal, s.redo_list,
+                           s.redo_count);
       else
-        hipLaunchKernelGGL(k_states_generic<false>, dim3(256), dim3(256), 0, st, s.sel, s.bc,
+        hipLaunchKernelGGL(k_states_generic<false>, dim3(32), dim3(256), 0, st, s.sel, s.bc,
                            s.yy, p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean,
-                           logL, top_mask, top_q, 0, B_acc, scal, s.redo_list, s.redo_count);
+                           logL, top_mask, top_q, 0, (float*)nullptr, Bat, scal, s.redo_list,
+                           s.redo_count);
     }
     return hipGetLastError();
   }
+  float* ss_out = acc ? s.ss : nullptr;
   int64_t blocks = (N + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (tsc)
     hipLaunchKernelGGL(k_states_generic<true>, dim3((unsigned)blocks), dim3(256), 0, st, s.sel,
                        s.bc, s.yy, p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean,
-                       logL, top_mask, top_q, topk, B_acc, scal, nullptr, nullptr);
+                       logL, top_mask, top_q, topk, ss_out, (float*)nullptr, scal, nullptr,
+                       nullptr);
   else
     hipLaunchKernelGGL(k_states_generic<false>, dim3((unsigned)blocks), dim3(256), 0, st, s.sel,
                        s.bc, s.yy, p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean,
-                       logL, top_mask, top_q, topk, B_acc, scal, nullptr, nullptr);
+                       logL, top_mask, top_q, topk, ss_out, (float*)nullptr, scal, nullptr,
+                       nullptr);
   return hipGetLastError();
 }
 

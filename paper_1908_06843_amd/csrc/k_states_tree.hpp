@@ -175,17 +175,33 @@ struct TscTree {
   }
 };
 
+// Everything one lane does for one data point: the walk and its per-point
+// results.  `ok` is false for a point handed to the exact kernel (and for
+// lanes without a point).
 template <int HP, int GAMMA, bool TSC>
-__global__ __launch_bounds__(64) void k_states_tree(
-    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
-    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
-    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ B_acc,
-    double* __restrict__ scal, int32_t* __restrict__ redo_list, int32_t* __restrict__ redo_count) {
-  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool live = n < N;
+struct PointResult {
+  float M[HP], K2[HP], P[HP][HP];
+  int s[HP];
+  float invZ, kmean;
+  double lL;
+  bool ok;
+};
+
+template <int HP, int GAMMA, bool TSC>
+__device__ __forceinline__ void tree_point(PointResult<HP, GAMMA, TSC>& R, int64_t n, bool live,
+                                           const int32_t* __restrict__ sel,
+                                           const float* __restrict__ bc,
+                                           const float* __restrict__ yy,
+                                           const float* __restrict__ G, int H, int64_t N,
+                                           const Theta* __restrict__ th,
+                                           int32_t* __restrict__ redo_list,
+                                           int32_t* __restrict__ redo_count) {
   const int64_t nn = live ? n : N - 1;
   const float lam2 = th->lam2, c1 = th->c1_2;
-  int s[HP];
+  int* s = R.s;
+  float (&M)[HP] = R.M;
+  float (&K2)[HP] = R.K2;
+  float (&P)[HP][HP] = R.P;
   float b[HP];
 #pragma unroll
   for (int j = 0; j < HP; ++j) {
@@ -197,7 +213,6 @@ __global__ __launch_bounds__(64) void k_states_tree(
   for (int i = 0; i < HP; ++i)
 #pragma unroll
     for (int j = i + 1; j < HP; ++j) p[i][j] = -2.0f * lam2 * G[(int64_t)s[i] * H + s[j]];
-  float M[HP], K2[HP], P[HP][HP];
 #pragma unroll
   for (int i = 0; i < HP; ++i) {
     M[i] = 0.0f;
@@ -248,39 +263,52 @@ __global__ __launch_bounds__(64) void k_states_tree(
     }
     Z = fast_exp2(-m) + TscTree<HP, GAMMA, 0u, 0u, -1, 0>::walk2(up, um, p, v0, 0.0f, m, M, K2, P);
   }
-  bool ok = live;
+  R.ok = live;
   if (GAMMA > 2 && live && !(Z < 1.8446744e19f)) {
-    ok = false;
+    R.ok = false;
     const int slot = atomicAdd(redo_count, 1);
     redo_list[slot] = (int32_t)n;
   }
-  // fresh copies of the latent indices: otherwise the G-gather offsets
-  // (s_i H + s_j) are kept alive to be reused by the B scatter below
+  // fresh copies of the latent indices (keeps the G-gather offsets from being
+  // held across the walk for reuse after it)
 #pragma unroll
   for (int j = 0; j < HP; ++j) opaque(s[j]);
-  const float invZ = 1.0f / Z;
-  const double lL = th->c0 - (double)th->lam * (double)yy[nn] +
-                    0.6931471805599453 * ((double)m + (double)log2f(Z));
-  float kmean = 0.0f;
+  R.invZ = 1.0f / Z;
+  R.lL = th->c0 - (double)th->lam * (double)yy[nn] +
+         0.6931471805599453 * ((double)m + (double)log2f(Z));
+  float km = 0.0f;
 #pragma unroll
-  for (int j = 0; j < HP; ++j) kmean += K2[j];
-  kmean *= invZ;
-  if (ok) {
-    if (logL) logL[n] = (float)lL;
+  for (int j = 0; j < HP; ++j) km += K2[j];
+  R.kmean = km * R.invZ;
+}
+
+// One lane per point, 64-lane workgroups; optional pair-major <s s^T>.
+template <int HP, int GAMMA, bool TSC>
+__global__ __launch_bounds__(64) void k_states_tree(
+    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
+    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
+    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ ss_out,
+    double* __restrict__ scal, int32_t* __restrict__ redo_list, int32_t* __restrict__ redo_count) {
+  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool live = n < N;
+  PointResult<HP, GAMMA, TSC> R;
+  tree_point<HP, GAMMA, TSC>(R, n, live, sel, bc, yy, G, H, N, th, redo_list, redo_count);
+  if (R.ok) {
+    if (logL) logL[n] = (float)R.lL;
 #pragma unroll
-    for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = M[j] * invZ;
-    if (B_acc) {
+    for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = R.M[j] * R.invZ;
+    if (ss_out) {  // pair-major: diagonal first, then i < j row-major
+      int q = HP;
 #pragma unroll
       for (int i = 0; i < HP; ++i) {
-        atomicAdd(&B_acc[(int64_t)s[i] * H + s[i]], K2[i] * invZ);
+        ss_out[(int64_t)i * N + n] = R.K2[i] * R.invZ;
 #pragma unroll
-        for (int j = i + 1; j < HP; ++j)
-          atomicAdd(&B_acc[(int64_t)s[i] * H + s[j]], P[i][j] * invZ);
+        for (int j = i + 1; j < HP; ++j) ss_out[(int64_t)(q++) * N + n] = R.P[i][j] * R.invZ;
       }
     }
   }
   if (scal) {
-    double a0 = ok ? (double)kmean : 0.0, a1 = ok ? lL : 0.0;
+    double a0 = R.ok ? (double)R.kmean : 0.0, a1 = R.ok ? R.lL : 0.0;
     a0 = wave_sum_d(a0);
     a1 = wave_sum_d(a1);
     if (threadIdx.x == 0) {
@@ -290,14 +318,93 @@ __global__ __launch_bounds__(64) void k_states_tree(
   }
 }
 
-// Defines the launcher of one compile-time shape.
+// Training variant: persistent 512-lane workgroups (8 waves, the occupancy the
+// walk's registers allow anyway) that also add every point's <s s^T> block
+// into a workgroup-private copy of B's packed upper triangle in LDS, then
+// store that partial with plain stores (partB[block]); the partials are
+// summed by the statistics reduction.  Requires H (H + 1) / 2 <= BSLICE floats.
+template <int HP, int GAMMA, bool TSC>
+__global__ __launch_bounds__(512) void k_states_tree_acc(
+    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
+    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
+    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ partB,
+    int64_t part_stride, double* __restrict__ scal, int32_t* __restrict__ redo_list,
+    int32_t* __restrict__ redo_count) {
+  extern __shared__ float Bl[];  // packed upper triangle, row h at h H - h (h - 1) / 2
+  __shared__ double red[2][8];
+  const int len = H * (H + 1) / 2;
+  for (int e = threadIdx.x; e < len; e += 512) Bl[e] = 0.0f;
+  __syncthreads();
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * 512; base < N; base += (int64_t)gridDim.x * 512) {
+    const int64_t n = base + threadIdx.x;
+    const bool live = n < N;
+    PointResult<HP, GAMMA, TSC> R;
+    tree_point<HP, GAMMA, TSC>(R, n, live, sel, bc, yy, G, H, N, th, redo_list, redo_count);
+    if (R.ok) {
+      if (logL) logL[n] = (float)R.lL;
+#pragma unroll
+      for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = R.M[j] * R.invZ;
+#pragma unroll
+      for (int i = 0; i < HP; ++i) {
+        const int hi = R.s[i];
+        const int row = hi * H - hi * (hi - 1) / 2 - hi;  // packed index of (hi, h2) = row + h2
+        atomicAdd(&Bl[row + hi], R.K2[i] * R.invZ);
+#pragma unroll
+        for (int j = i + 1; j < HP; ++j) atomicAdd(&Bl[row + R.s[j]], R.P[i][j] * R.invZ);
+      }
+      a0 += (double)R.kmean;
+      a1 += R.lL;
+    }
+  }
+  __syncthreads();
+  float* out = partB + (int64_t)blockIdx.x * part_stride;
+  for (int e = threadIdx.x; e < len; e += 512) out[e] = Bl[e];
+  if (scal) {
+    a0 = wave_sum_d(a0);
+    a1 = wave_sum_d(a1);
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = a0;
+      red[1][threadIdx.x >> 6] = a1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int w = 0; w < 8; ++w) {
+        t0 += red[0][w];
+        t1 += red[1][w];
+      }
+      atomicAdd(&scal[0], t0);
+      atomicAdd(&scal[1], t1);
+    }
+  }
+}
+
+// Defines the launchers of one compile-time shape: acc_blocks = 0 runs the
+// plain kernel; otherwise the training variant on acc_blocks workgroups.
 #define PROSPER_TREE_INSTANCE(TSCV, HPV, GMV)                                                    \
   hipError_t launch_tree_##TSCV##_##HPV##_##GMV(const Prepared& p, const Scratch& s, int64_t N,  \
-                                                int H, float* logL, float* B_acc, double* scal,  \
+                                                int H, float* logL, float* ss_out, double* scal, \
+                                                int acc_blocks, float* partB, int64_t stride,    \
                                                 hipStream_t st) {                                \
+    if (acc_blocks > 0) {                                                                        \
+      auto kern = k_states_tree_acc<HPV, GMV, TSCV>;                                             \
+      const size_t lds = (size_t)H * (H + 1) / 2 * 4;                                            \
+      static size_t configured = 0;                                                              \
+      if (lds > configured) {                                                                    \
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                  \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);\
+        if (e != hipSuccess) return e;                                                           \
+        configured = lds;                                                                        \
+      }                                                                                          \
+      hipLaunchKernelGGL(kern, dim3((unsigned)acc_blocks), dim3(512), lds, st, s.sel, s.bc,      \
+                         s.yy, p.G, H, N, p.theta, s.s_mean, logL, partB, stride, scal,          \
+                         s.redo_list, s.redo_count);                                             \
+      return hipGetLastError();                                                                  \
+    }                                                                                            \
     hipLaunchKernelGGL((k_states_tree<HPV, GMV, TSCV>), dim3((unsigned)((N + 63) / 64)),         \
                        dim3(64), 0, st, s.sel, s.bc, s.yy, p.G, H, N, p.theta, s.s_mean, logL,   \
-                       B_acc, scal, s.redo_list, s.redo_count);                                  \
+                       ss_out, scal, s.redo_list, s.redo_count);                                 \
     return hipGetLastError();                                                                    \
   }
 

@@ -45,14 +45,27 @@ struct Prepared {
   Theta* theta;     // 1
 };
 
+// A += y <s>^T and B += <s s^T> through per-group LDS partials (no global atomics).
+static constexpr int STATS_MAX_BSLICES = 32;
+struct StatsPlan {
+  int DS = 64, nA = 1, nB = 1, ngroups = 1, mfma_wgs = 256;
+  int64_t ppg = 1;
+  size_t partA_floats = 0, partB_floats = 0;
+};
+StatsPlan stats_plan(int64_t N, int D, int H, int num_cu);
+
 // Per-call intermediates (device).
 struct Scratch {
   int32_t* sel;     // N x H'
   float* bc;        // N x H'   candidate projections b_{I_n(j)} (signed)
   float* yy;        // N        ||y_n||^2 (FP32)
   float* s_mean;    // N x H'
+  float* ss;        // H'(H'+1)/2 x N  <s_i s_j> per point, pair-major (statistics only)
   int32_t* redo_list;   // N   points the unrolled walk hands to the exact kernel
   int32_t* redo_count;  // 1   (cleared by the parameter kernel of each call)
+  float* partA;         // statistics: per-group partials of A and B
+  float* partB;
+  StatsPlan plan;
 };
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -88,20 +101,29 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
                                  int H, int Hp, const Prepared& p, const Scratch& s,
                                  uint8_t* flagged, double* scal, hipStream_t st);
 // BSC / TSC state walk.  tab_act/tab_sgn: canonical state table on the device.
+// Statistics mode of the linear state walk (acc != NULL): either the
+// training tree kernel writes per-workgroup B partials (returns the number
+// of partials in *tree_blocks), or the walk writes pair-major <s s^T> into
+// s.ss for the statistics kernel (*tree_blocks = 0).  Points handed to the
+// exact kernel add their <s s^T> straight into acc_B with atomics.
 hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int64_t nstates,
                              const uint32_t* tab_act, const uint32_t* tab_sgn,
                              const Prepared& p, const Scratch& s, float* logL,
-                             uint32_t* top_mask, float* top_q, int topk,
-                             float* B_acc, double* scal, hipStream_t st);
+                             uint32_t* top_mask, float* top_q, int topk, bool acc,
+                             float* acc_B, double* scal, int num_cu, int* tree_blocks,
+                             hipStream_t st);
 // MCA state walk (max superposition).
 hipError_t launch_states_max(int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
                              const uint32_t* tab_act, const float* Y, const Prepared& p,
                              const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, float* A_num, float* B_den, double* scal,
                              hipStream_t st);
-// A += y <s>^T on the candidate columns.
-hipError_t launch_accum_A(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
-                          float* A, int num_cu, hipStream_t st);
+int stats_bslice_floats();
+bool stats_a_mfma_ok(int D, int H);
+int stats_bslice_count(int H);
+hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
+                        const StatsPlan& pl, int tree_blocks, float* A, float* B,
+                        hipStream_t st);
 // M-step.
 size_t mstep_workspace_bytes(int model, int D, int H);
 hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,

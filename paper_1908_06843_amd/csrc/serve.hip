@@ -195,6 +195,8 @@ void launch(prosper_server* s, Req* r) {
   sc.s_mean = reinterpret_cast<float*>(dev + r->o_sm);
   sc.redo_list = reinterpret_cast<int32_t*>(dev + r->o_redo);
   sc.redo_count = reinterpret_cast<int32_t*>(dev + r->o_cnt);
+  sc.ss = nullptr;
+  sc.partA = sc.partB = nullptr;
   float* logL = reinterpret_cast<float*>(dev + r->o_logL);
   uint8_t* flag = reinterpret_cast<uint8_t*>(dev + r->o_flag);
   uint32_t* tm = r->topk ? reinterpret_cast<uint32_t*>(dev + r->o_tm) : nullptr;
