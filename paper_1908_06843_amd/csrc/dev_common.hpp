@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace prosper {
 
@@ -48,6 +49,23 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 __device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
   p = a * b;
   e = __builtin_fmaf(a, b, -p);
+}
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// 64-bit value of lane `lane` (uniform index) as a wave-uniform scalar.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }

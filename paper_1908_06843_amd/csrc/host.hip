@@ -350,7 +350,7 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
                              uint8_t* flagged, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, float* A, float* B, double* scal, int num_cu,
                              hipStream_t s) {
-  const int Dp = round_up(D, 32);
+  const int Dp = padded_depth(D);
   hipError_t e = launch_project_select(model, prec, Y, N, D, Dp, H, Hp, p, sc, flagged, scal, s);
   if (e != hipSuccess) return e;
   if (model == PROSPER_MCA)
@@ -496,7 +496,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   const int model = a->model, prec = a->precision;
   const int64_t N = a->N;
   const int D = a->D, H = a->H, Hp = a->Hprime;
-  const int Dp = round_up(D, 32);
+  const int Dp = padded_depth(D);
 
   Table* tab = nullptr;
   st = get_table(c, model, Hp, a->gamma, &tab);

@@ -9,20 +9,22 @@
 //   r_h = |b_h| - 1/2 ||P_h||^2         (TSC: better of the two signs)
 //
 // Selection is exact with respect to the real-valued scores: the projection
-// error is bounded by delta (the standard FP32 summation bound plus, for the
-// BF16 split, the representation error of the head/tail pair), and whenever
-// the H'-th and (H'+1)-th computed scores lie within 2 delta the latents in
-// that band are re-scored with a compensated FP32 dot product (TwoProduct +
-// TwoSum), which leaves only genuine near-ties undecided.  Such points are
-// flagged when the refined gap is within 1e-6 max(1, |r|).
+// error is bounded by delta (the FP32 summation bound plus, for the BF16
+// split, the representation error of the head/tail pair).  A point whose
+// H'-th and (H'+1)-th computed scores are further apart than 2 delta is
+// decided by the computed scores; otherwise the latents in the undecided
+// band are re-scored with a compensated FP32 dot product (TwoProduct +
+// TwoSum), which leaves only genuine near-ties, flagged when the refined gap
+// is within 1e-6 max(1, |r|).
 //
 // MFMA layouts (CDNA wave64, 16x16 output tile, lane l: row/col l%16):
 //   v_mfma_f32_16x16x4_f32  : A[l%16][k-group l/16], one k per lane
 //   v_mfma_f32_16x16x32_bf16: A[l%16][8 consecutive k of group l/16]
 //   C: 4 values per lane at rows 4(l/16)+i, column l%16
-// The k index of group q runs over a contiguous quarter of the padded depth
-// (k = q Dp/4 + t) so that each lane reads 16 contiguous bytes per step; A
-// and B use the same map, so the contraction is unchanged.
+// Within each block of 64 depths, lane group q owns depths 16 q .. 16 q + 15
+// (spread over the block's MFMAs), so the four groups of a row read one
+// whole cache line of P per block; A and B use the same map, so the
+// contraction is unchanged.
 #include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
@@ -75,69 +77,370 @@ __device__ __forceinline__ void radix_select(const uint32_t (&key)[RM], int R, i
   }
 }
 
-template <int PREC, int TM, int RM>
+// Running list of the KL largest values (descending) without indices:
+// a new value bubbles down by max/min pairs.
+template <int KL>
+__device__ __forceinline__ void list_insert(float (&t)[KL], float v) {
+  static_for<0, KL>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const float hi = fmaxf(t[k], v);
+    v = fminf(t[k], v);
+    t[k] = hi;
+  });
+}
+
+template <int KL>
+__device__ __forceinline__ float list_at(const float (&t)[KL], int i) {
+  float r = t[0];
+  static_for<1, KL>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    r = (i == k) ? t[k] : r;
+  });
+  return r;
+}
+
+// Sum over the 64 lanes of RPW per-lane values at once (butterfly
+// reduce-scatter): afterwards lanes whose index is a multiple of 64/RPW hold
+// the total of value `row` (returned).
+template <int RPW>
+__device__ __forceinline__ int wave_sum_rows(double (&v)[RPW], int lane, double& total) {
+  int row = 0;
+  static_for<0, 6>([&](auto sc) {
+    constexpr int st = decltype(sc)::value;
+    constexpr int off = 32 >> st;
+    constexpr int half = RPW >> (st + 1);
+    if constexpr (half >= 1) {
+      const bool upper = (lane & off) != 0;
+      static_for<0, half>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const double keep = upper ? v[i + half] : v[i];
+        const double send = upper ? v[i] : v[i + half];
+        v[i] = keep + __shfl_xor(send, off, 64);
+      });
+      if (upper) row += half;
+    } else {
+      v[0] += __shfl_xor(v[0], off, 64);
+    }
+  });
+  total = v[0];
+  return row;
+}
+
+// Exact selection of one point by one wave from its score row (lane l holds
+// the latents 64 i + l).  cH and cN are the H'-th and (H'+1)-th largest
+// computed scores: given by the caller (have_thr), else found by a radix
+// select.  With every computed score within delta of the real one, a latent
+// scoring above cH + 2 delta is certainly among the H' best and one below
+// cN - 2 delta certainly is not; the latents in between (the band U) are
+// re-scored with a compensated dot product (TwoProduct + TwoSum), and the
+// missing H' - |C| are taken from U by refined score (ties to the lower
+// index).  The point is flagged when the refined H'-th and (H'+1)-th scores
+// are within 1e-6 max(1, |r|).
+template <int RM>
+__device__ __forceinline__ void exact_select_point(const float* __restrict__ brow, int lane, int R, int H, int Hp,
+                                   int score_abs, bool have_thr, float cH, float cN, float delta,
+                                   const float* __restrict__ yrow, int D, int Dp,
+                                   const float* __restrict__ Pt32,
+                                   const float* __restrict__ hn_hi,
+                                   const float* __restrict__ hn_lo, int32_t* __restrict__ selp,
+                                   float* __restrict__ bcp, uint8_t* flagp) {
+  float b[RM], sc[RM];
+  uint32_t key[RM];
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    const int h = 64 * i + lane;
+    const bool valid = (i < R) && (h < H);
+    b[i] = (i < R) ? brow[h] : 0.0f;
+    const float bb = score_abs ? fabsf(b[i]) : b[i];
+    sc[i] = valid ? (bb - hn_hi[h < H ? h : 0]) - hn_lo[h < H ? h : 0] : 0.0f;
+    key[i] = valid ? f2key(sc[i]) : 0u;
+  }
+  uint64_t selm[RM];
+  uint8_t flag = 0;
+  if (Hp >= H) {
+#pragma unroll
+    for (int i = 0; i < RM; ++i) selm[i] = ballot64((i < R) && (64 * i + lane < H));
+  } else {
+    if (!have_thr) {
+      radix_select<RM>(key, R, Hp, selm);
+      float mH = INFINITY, mN = -INFINITY;
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        const bool valid = (i < R) && (64 * i + lane < H);
+        if (valid) {
+          if ((selm[i] >> lane) & 1ull) mH = fminf(mH, sc[i]);
+          else mN = fmaxf(mN, sc[i]);
+        }
+      }
+      cH = wave_min(mH);
+      cN = wave_max(mN);
+    }
+    const float gap = cH - cN;
+    if (!(gap > 2.0f * delta) || !(gap > 1e-6f * fmaxf(1.0f, fabsf(cH)))) {
+      const float lo_b = cN - 2.0f * delta, hi_b = cH + 2.0f * delta;
+      uint64_t Um[RM], Cm[RM];
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        const bool valid = (i < R) && (64 * i + lane < H);
+        Um[i] = ballot64(valid && sc[i] >= lo_b && sc[i] <= hi_b);
+        Cm[i] = ballot64(valid && sc[i] > hi_b);
+      }
+      // re-score the band, four latents at a time, 256 depths per round:
+      // every load of a round is issued before the first use
+      uint64_t rem[RM];
+#pragma unroll
+      for (int i = 0; i < RM; ++i) rem[i] = Um[i];
+      while (true) {
+        int hs[4];
+        int cnt = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          int h = -1;
+#pragma unroll
+          for (int i = 0; i < RM; ++i) {
+            if (h < 0 && rem[i] != 0ull) {
+              h = 64 * i + __ffsll((unsigned long long)rem[i]) - 1;
+              rem[i] &= rem[i] - 1ull;
+            }
+          }
+          hs[m] = h;
+          cnt += h >= 0 ? 1 : 0;
+        }
+        if (cnt == 0) break;
+        float ss[4] = {0.f, 0.f, 0.f, 0.f}, cc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int d0 = 0; d0 < D; d0 += 256) {
+          float yv[4], pv[4][4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int d = d0 + 64 * k + lane;
+            const float y = yrow[d < D ? d : D - 1];
+            yv[k] = d < D ? y : 0.0f;
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int d = d0 + 64 * k + lane;
+              const int hm = hs[m] >= 0 ? hs[m] : hs[0];
+              pv[m][k] = Pt32[(int64_t)hm * Dp + (d < D ? d : D - 1)];
+            }
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              float pr, e, s2, e2;
+              two_prod(yv[k], pv[m][k], pr, e);
+              two_sum(ss[m], pr, s2, e2);
+              ss[m] = s2;
+              cc[m] += e2 + e;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if (m < cnt) {
+            float s = ss[m], c = cc[m];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+              const float so = __shfl_xor(s, o, 64), co = __shfl_xor(c, o, 64);
+              float s2, e2;
+              two_sum(s, so, s2, e2);
+              s = s2;
+              c = c + co + e2;
+            }
+            const int h = hs[m];
+            const float sg = (score_abs && s < 0.0f) ? -1.0f : 1.0f;
+            const float rr = (sg * s - hn_hi[h]) + (sg * c - hn_lo[h]);
+            const int i = h >> 6, l2 = h & 63;
+#pragma unroll
+            for (int i2 = 0; i2 < RM; ++i2) {
+              if (i2 == i && lane == l2) {
+                sc[i2] = rr;
+                b[i2] = s + c;
+                key[i2] = f2key(rr);
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        if (!((Um[i] >> lane) & 1ull)) key[i] = ((Cm[i] >> lane) & 1ull) ? 0xFFFFFFFFu : 0u;
+      }
+      radix_select<RM>(key, R, Hp, selm);
+      float uH = INFINITY, uN = -INFINITY;
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        if ((Um[i] >> lane) & 1ull) {
+          if ((selm[i] >> lane) & 1ull) uH = fminf(uH, sc[i]);
+          else uN = fmaxf(uN, sc[i]);
+        }
+      }
+      uH = wave_min(uH);
+      uN = wave_max(uN);
+      flag = (uH - uN <= 1e-6f * fmaxf(1.0f, fabsf(uH))) ? 1 : 0;
+    } else {
+      // the threshold decides
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        const bool valid = (i < R) && (64 * i + lane < H);
+        selm[i] = ballot64(valid && sc[i] >= cH);
+      }
+    }
+  }
+  int base = 0;
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    const uint64_t m = selm[i];
+    if ((m >> lane) & 1ull) {
+      const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+      selp[pos] = 64 * i + lane;
+      bcp[pos] = b[i];
+    }
+    base += __popcll(m);
+  }
+  if (lane == 0 && flagp) *flagp = flag;
+}
+
+// Selection lists of the lane-per-point pass (H' <= FAST_HP).
+static constexpr int FAST_HP = 12;
+static constexpr int FAST_KL = FAST_HP + 1;
+
+template <int TM>
+struct SelLds {
+  union {
+    float lists[3][FAST_KL][TM];    // per-quarter running lists of waves 1..3
+    uint16_t qsel[4][TM][FAST_HP];  // selected latents found by each quarter
+  } u;
+  uint8_t qcnt[4][TM];
+  float thr[TM];
+  float thrN[TM];
+  uint8_t fast[TM];
+  uint8_t slow[TM];
+  int nslow;
+};
+
+// One workgroup (4 waves) per tile of TM points:
+//   1. Y tile -> LDS (FP32, or BF16 head/tail), ||y||^2 in FP64;
+//   2. b = P y by MFMA, the next B fragments prefetched during each step;
+//   3. b -> LDS score tile (row per point, odd stride);
+//   4. FAST (H' <= 12 < H): every lane takes one point; wave w keeps the
+//      H'+1 largest scores of latent quarter w, wave 0 merges the four lists.
+//      A point whose H'-th and (H'+1)-th scores are further apart than the
+//      error bound 2 delta (and the flag distance) is decided by threshold:
+//      its selection is every latent scoring at least the H'-th value.  The
+//      remaining points go through the exact per-wave path above.
+//      Without FAST every point takes the exact path.
+template <int PREC, int TM, int RM, bool FAST>
 __global__ __launch_bounds__(256, 2) void k_project_select(
     const float* __restrict__ Y, int64_t N, int D, int Dp, int H,
     const float* __restrict__ Pt32, const bf16* __restrict__ Pt_hi,
     const bf16* __restrict__ Pt_lo, const float* __restrict__ hn_hi,
     const float* __restrict__ hn_lo, const float* __restrict__ pnorm, int Hp, int score_abs,
     float kappa, int32_t* __restrict__ sel, float* __restrict__ bc, float* __restrict__ yy_out,
-    uint8_t* __restrict__ flagged, double* __restrict__ scal) {
+    uint8_t* __restrict__ flagged, double* __restrict__ scal, int tile_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float yyS[TM];
   __shared__ double yydS[TM];
+  __shared__ SelLds<TM> sl;
   constexpr int MT = TM / 16;       // point tiles of 16
   constexpr int GPW = 4 / MT;       // latent groups (of 64) per wave
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int RPW = TM / 4;       // staged rows per wave
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int q = lane >> 4, r16 = lane & 15;
   const int64_t n0 = (int64_t)blockIdx.x * TM;
   const int Hpad = round_up(H, 64);
-  const int Hs = Hpad + 4;
+  const int Hs = Hpad + 1;
   const int ngroups = Hpad / 64;
-  const int kq = Dp / 4;
+  // 1/2 ||P_h||^2 (head, tail) of every latent, behind the tile in LDS
+  float* hnS = reinterpret_cast<float*>(smem + tile_bytes);
+  for (int h = threadIdx.x; h < Hpad; h += 256) {
+    hnS[h] = h < H ? hn_hi[h] : 0.0f;
+    hnS[Hpad + h] = h < H ? hn_lo[h] : 0.0f;
+  }
 
-  // ---- stage the Y tile (FP32, or BF16 head/tail) and ||y||^2 in FP64
-  if constexpr (PREC == PROSPER_FP32) {
-    float* Ys = reinterpret_cast<float*>(smem);
-    const int ys = Dp + 4;
-    for (int r = wave; r < TM; r += 4) {
-      const int64_t n = n0 + r;
-      double acc = 0.0;
-      for (int d = lane; d < Dp; d += 64) {
-        float v = (n < N && d < D) ? Y[n * D + d] : 0.0f;
-        Ys[r * ys + d] = v;
-        acc = fma((double)v, (double)v, acc);
+  // ---- 1. stage the Y tile: every load of a lane issued before any use
+  {
+    const int nc4 = Dp >> 2;            // float4 per padded row
+    const int cj = (nc4 + 63) >> 6;     // per lane and row (<= 4)
+    const bool vec = (D & 3) == 0;
+    double part[RPW];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) part[rr] = 0.0;
+    for (int j = 0; j < cj; ++j) {
+      const int c4 = lane + 64 * j;
+      // unconditional loads from clamped addresses (masked afterwards), so
+      // that the RPW loads of a lane are all in flight together
+      float4 v[RPW];
+      if (vec) {
+        const bool cok = 4 * c4 < D;
+        const int cc = cok ? 4 * c4 : 0;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+          const int64_t n = n0 + wave * RPW + rr;
+          const int64_t nn = n < N ? n : N - 1;
+          const float4 x = *reinterpret_cast<const float4*>(Y + nn * D + cc);
+          v[rr] = (cok && n < N) ? x : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      } else {
+        const int d = 4 * c4;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+          const int64_t n = n0 + wave * RPW + rr;
+          const bool nok = n < N;
+          const float* yr = Y + (nok ? n : N - 1) * D;
+          float e[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float x = yr[min(d + k, D - 1)];
+            e[k] = (nok && d + k < D) ? x : 0.f;
+          }
+          v[rr] = make_float4(e[0], e[1], e[2], e[3]);
+        }
       }
-      acc = wave_sum_d(acc);
-      if (lane == 0) {
-        yyS[r] = (float)acc;
-        yydS[r] = acc;
+      if (c4 < nc4) {
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+          const int r = wave * RPW + rr;
+          const float4 x = v[rr];
+          if constexpr (PREC == PROSPER_FP32) {
+            float* Ys = reinterpret_cast<float*>(smem);
+            *reinterpret_cast<float4*>(&Ys[r * (Dp + 4) + 4 * c4]) = x;
+          } else {
+            bf16* Yh = reinterpret_cast<bf16*>(smem);
+            bf16* Yl = Yh + TM * (Dp + 8);
+            typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+            bf16x4 hi, lo;
+            hi[0] = (bf16)x.x;
+            hi[1] = (bf16)x.y;
+            hi[2] = (bf16)x.z;
+            hi[3] = (bf16)x.w;
+            lo[0] = (bf16)(x.x - (float)hi[0]);
+            lo[1] = (bf16)(x.y - (float)hi[1]);
+            lo[2] = (bf16)(x.z - (float)hi[2]);
+            lo[3] = (bf16)(x.w - (float)hi[3]);
+            *reinterpret_cast<bf16x4*>(&Yh[r * (Dp + 8) + 4 * c4]) = hi;
+            *reinterpret_cast<bf16x4*>(&Yl[r * (Dp + 8) + 4 * c4]) = lo;
+          }
+          double a = part[rr];
+          a = fma((double)x.x, (double)x.x, a);
+          a = fma((double)x.y, (double)x.y, a);
+          a = fma((double)x.z, (double)x.z, a);
+          a = fma((double)x.w, (double)x.w, a);
+          part[rr] = a;
+        }
       }
     }
-  } else {
-    bf16* Yh = reinterpret_cast<bf16*>(smem);
-    const int ys = Dp + 8;
-    bf16* Yl = Yh + TM * ys;
-    for (int r = wave; r < TM; r += 4) {
-      const int64_t n = n0 + r;
-      double acc = 0.0;
-      for (int d = lane; d < Dp; d += 64) {
-        float v = (n < N && d < D) ? Y[n * D + d] : 0.0f;
-        bf16 hi = (bf16)v;
-        Yh[r * ys + d] = hi;
-        Yl[r * ys + d] = (bf16)(v - (float)hi);
-        acc = fma((double)v, (double)v, acc);
-      }
-      acc = wave_sum_d(acc);
-      if (lane == 0) {
-        yyS[r] = (float)acc;
-        yydS[r] = acc;
-      }
+    double tot;
+    const int rr = wave_sum_rows<RPW>(part, lane, tot);
+    if ((lane & (64 / RPW - 1)) == 0) {
+      yyS[wave * RPW + rr] = (float)tot;
+      yydS[wave * RPW + rr] = tot;
     }
   }
   __syncthreads();
 
-  // ---- b = P y for the tile: MFMA, FP32 accumulation
+  // ---- 2. b = P y for the tile: MFMA, FP32 accumulation
   f32x4 acc[4][4];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
@@ -148,72 +451,122 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
   for (int gi = 0; gi < GPW; ++gi) {
     const int g = wave + 4 * gi;
     if (g >= ngroups) break;
+    // B rows of this lane (clamped inside P; rows >= H are zeroed)
+    int64_t boff[4];
+    bool bval[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int h = g * 64 + nt * 16 + r16;
+      bval[nt] = h < H;
+      boff[nt] = (int64_t)(h < H ? h : H - 1) * Dp + 16 * q;
+    }
+    // k order inside a block of 64 depths: lane group q owns the 16
+    // consecutive depths [16 q, 16 q + 16), so the four groups of a row read
+    // one whole 128-byte line of P per block; A fragments use the same order.
     if constexpr (PREC == PROSPER_FP32) {
+      // 16x16x4 FP32: MFMA m (0..15) of a block takes depth 16 q + m of lane group q
       const float* Ys = reinterpret_cast<const float*>(smem);
       const int ys = Dp + 4;
-      for (int t = 0; t < kq; t += 4) {
-        float4 a[MT], b[4];
+      float4 b[4][4], bn[4][4];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          a[mt] = *reinterpret_cast<const float4*>(&Ys[(mt * 16 + r16) * ys + q * kq + t]);
+      for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const int h = g * 64 + nt * 16 + r16;
-          b[nt] = (h < H) ? *reinterpret_cast<const float4*>(&Pt32[(int64_t)h * Dp + q * kq + t])
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        for (int v = 0; v < 4; ++v)
+          b[nt][v] = *reinterpret_cast<const float4*>(&Pt32[boff[nt] + 4 * v]);
+      for (int t = 0; t < Dp; t += 64) {
+        const int tn = (t + 64 < Dp) ? t + 64 : t;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            bn[nt][v] = *reinterpret_cast<const float4*>(&Pt32[boff[nt] + tn + 4 * v]);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (!bval[nt]) b[nt][v] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          float4 a[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            a[v] = *reinterpret_cast<const float4*>(&Ys[(mt * 16 + r16) * ys + t + 16 * q + 4 * v]);
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt) {
             f32x4& c = acc[gi * MT + mt][nt];
-            c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].x, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].y, b[nt].y, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].z, b[nt].z, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].w, b[nt].w, c, 0, 0, 0);
-          }
-      }
-    } else {
-      const bf16* Yh = reinterpret_cast<const bf16*>(smem);
-      const int ys = Dp + 8;
-      const bf16* Yl = Yh + TM * ys;
-      for (int t = 0; t < kq; t += 8) {
-        bf16x8 ah[MT], al[MT], bh[4], bl[4];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int o = (mt * 16 + r16) * ys + q * kq + t;
-          ah[mt] = *reinterpret_cast<const bf16x8*>(&Yh[o]);
-          al[mt] = *reinterpret_cast<const bf16x8*>(&Yl[o]);
-        }
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const int h = g * 64 + nt * 16 + r16;
-          if (h < H) {
-            const int64_t o = (int64_t)h * Dp + q * kq + t;
-            bh[nt] = *reinterpret_cast<const bf16x8*>(&Pt_hi[o]);
-            bl[nt] = *reinterpret_cast<const bf16x8*>(&Pt_lo[o]);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              bh[nt][e] = (bf16)0.0f;
-              bl[nt][e] = (bf16)0.0f;
+            for (int v = 0; v < 4; ++v) {
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[v].x, b[nt][v].x, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[v].y, b[nt][v].y, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[v].z, b[nt][v].z, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[v].w, b[nt][v].w, c, 0, 0, 0);
             }
           }
         }
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) b[nt][v] = bn[nt][v];
+      }
+    } else {
+      // 16x16x32 BF16: MFMA j (0, 1) of a block takes depths 16 q + 8 j .. + 8
+      const bf16* Yh = reinterpret_cast<const bf16*>(smem);
+      const int ys = Dp + 8;
+      const bf16* Yl = Yh + TM * ys;
+      typedef __attribute__((ext_vector_type(4))) int i32x4;
+      i32x4 bh[4][2], bl[4][2], bhn[4][2], bln[4][2];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          bh[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_hi[boff[nt] + 8 * j]);
+          bl[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_lo[boff[nt] + 8 * j]);
+        }
+      for (int t = 0; t < Dp; t += 64) {
+        const int tn = (t + 64 < Dp) ? t + 64 : t;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            bhn[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_hi[boff[nt] + tn + 8 * j]);
+            bln[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_lo[boff[nt] + tn + 8 * j]);
+          }
+        const i32x4 zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          bf16x8 ah[MT], al[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const int o = (mt * 16 + r16) * ys + t + 16 * q + 8 * j;
+            ah[mt] = *reinterpret_cast<const bf16x8*>(&Yh[o]);
+            al[mt] = *reinterpret_cast<const bf16x8*>(&Yl[o]);
+          }
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt) {
-            f32x4& c = acc[gi * MT + mt][nt];
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh[nt], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl[nt], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh[nt], c, 0, 0, 0);
+            const bf16x8 bhv = __builtin_bit_cast(bf16x8, bval[nt] ? bh[nt][j] : zero);
+            const bf16x8 blv = __builtin_bit_cast(bf16x8, bval[nt] ? bl[nt][j] : zero);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+              f32x4& c = acc[gi * MT + mt][nt];
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bhv, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], blv, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bhv, c, 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            bh[nt][j] = bhn[nt][j];
+            bl[nt][j] = bln[nt][j];
           }
       }
     }
   }
   __syncthreads();  // the Y tile is dead from here on; Bs reuses its memory
 
+  // ---- 3. scores tile
   float* Bs = reinterpret_cast<float*>(smem);
 #pragma unroll
   for (int gi = 0; gi < GPW; ++gi) {
@@ -229,127 +582,115 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
   }
   __syncthreads();
 
-  // ---- per point: scores, exact top-H', outputs (one wave per point)
   const int R = Hpad / 64;
-  float hnh[RM], hnl[RM];
-#pragma unroll
-  for (int i = 0; i < RM; ++i) {
-    const int h = 64 * i + lane;
-    hnh[i] = (i < R && h < H) ? hn_hi[h] : 0.0f;
-    hnl[i] = (i < R && h < H) ? hn_lo[h] : 0.0f;
-  }
   const float pn = *pnorm;
-
-  for (int r = wave; r < TM; r += 4) {
-    const int64_t n = n0 + r;
-    if (n >= N) break;
-    float b[RM], sc[RM];
-    uint32_t key[RM];
+  if constexpr (FAST) {
+    // ---- 4a. per-quarter running lists (lane = point)
+    const int Q = Hpad / 4;
+    const int hq0 = wave * Q;
+    const int hq1 = min(hq0 + Q, H);
+    const int p = lane;
+    const bool plane = p < TM;
+    const float* brow = Bs + (plane ? p : 0) * Hs;
+    float tl[FAST_KL];
 #pragma unroll
-    for (int i = 0; i < RM; ++i) {
-      const int h = 64 * i + lane;
-      const bool valid = (i < R) && (h < H);
-      b[i] = (i < R) ? Bs[r * Hs + h] : 0.0f;
-      const float bb = score_abs ? fabsf(b[i]) : b[i];
-      sc[i] = (bb - hnh[i]) - hnl[i];
-      key[i] = valid ? f2key(sc[i]) : 0u;
+    for (int k = 0; k < FAST_KL; ++k) tl[k] = -INFINITY;
+#pragma unroll 8
+    for (int h = hq0; h < hq1; ++h) {
+      const float bv = brow[h];
+      const float bb = score_abs ? fabsf(bv) : bv;
+      list_insert<FAST_KL>(tl, (bb - hnS[h]) - hnS[Hpad + h]);
     }
-    uint64_t selm[RM];
-    uint8_t flag = 0;
-    if (Hp >= H) {
+    if (wave > 0 && plane) {
 #pragma unroll
-      for (int i = 0; i < RM; ++i) selm[i] = ballot64((i < R) && (64 * i + lane < H));
-    } else {
-      radix_select<RM>(key, R, Hp, selm);
-      float cH = INFINITY, cN = -INFINITY;
-#pragma unroll
-      for (int i = 0; i < RM; ++i) {
-        const bool valid = (i < R) && (64 * i + lane < H);
-        if (valid) {
-          if ((selm[i] >> lane) & 1ull) cH = fminf(cH, sc[i]);
-          else cN = fmaxf(cN, sc[i]);
+      for (int k = 0; k < FAST_KL; ++k) sl.u.lists[wave - 1][k][p] = tl[k];
+    }
+    __syncthreads();
+    // ---- 4b. merge, threshold, fast / exact decision
+    if (wave == 0) {
+      if (plane) {
+        for (int w2 = 0; w2 < 3; ++w2)
+          for (int k = 0; k <= Hp; ++k) list_insert<FAST_KL>(tl, sl.u.lists[w2][k][p]);
+      }
+      const int64_t n = n0 + p;
+      const bool valid = plane && n < N;
+      const float cH = list_at<FAST_KL>(tl, Hp - 1), cN = list_at<FAST_KL>(tl, Hp);
+      const float ynorm = sqrtf(valid ? yyS[p] : 0.0f);
+      const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+      const float gap = cH - cN;
+      const bool fast = valid && gap > 2.0f * delta && gap > 1e-6f * fmaxf(1.0f, fabsf(cH));
+      const uint64_t slowm = ballot64(valid && !fast);
+      if (plane) {
+        sl.thr[p] = cH;
+        sl.thrN[p] = cN;
+        sl.fast[p] = fast ? 1 : 0;
+        if (valid && !fast) sl.slow[__popcll(slowm & ((1ull << lane) - 1ull))] = (uint8_t)p;
+      }
+      if (lane == 0) sl.nslow = __popcll(slowm);
+    }
+    __syncthreads();
+    // ---- 4c. each quarter lists its latents at or above the threshold
+    if (plane) {
+      const bool f = sl.fast[p] != 0;
+      const float th = sl.thr[p];
+      int cnt = 0;
+#pragma unroll 8
+      for (int h = hq0; h < hq1; ++h) {
+        const float bv = brow[h];
+        const float bb = score_abs ? fabsf(bv) : bv;
+        const float v = (bb - hnS[h]) - hnS[Hpad + h];
+        if (f && v >= th && cnt < FAST_HP) {
+          sl.u.qsel[wave][p][cnt] = (uint16_t)h;
+          ++cnt;
         }
       }
-      cH = wave_min(cH);
-      cN = wave_max(cN);
+      sl.qcnt[wave][p] = (uint8_t)cnt;
+    }
+    __syncthreads();
+    // ---- 4d. outputs of the threshold-decided points (coalesced tile rows)
+    for (int e = threadIdx.x; e < TM * Hp; e += 256) {
+      const int pp = e / Hp, pos = e - pp * Hp;
+      const int64_t n = n0 + pp;
+      if (n < N && sl.fast[pp]) {
+        int rem = pos, w = 0;
+        while (w < 3 && rem >= sl.qcnt[w][pp]) {
+          rem -= sl.qcnt[w][pp];
+          ++w;
+        }
+        const int h = sl.u.qsel[w][pp][rem < FAST_HP ? rem : FAST_HP - 1];
+        sel[n * Hp + pos] = h;
+        bc[n * Hp + pos] = Bs[pp * Hs + h];
+      }
+    }
+    if (threadIdx.x < TM) {
+      const int64_t n = n0 + threadIdx.x;
+      if (n < N && sl.fast[threadIdx.x]) {
+        yy_out[n] = yyS[threadIdx.x];
+        if (flagged) flagged[n] = 0;
+      }
+    }
+    // ---- 4e. the exact path for the rest
+    const int ns = sl.nslow;
+    for (int i = wave; i < ns; i += 4) {
+      const int r = sl.slow[i];
+      const int64_t n = n0 + r;
       const float ynorm = sqrtf(yyS[r]);
       const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
-      if (!(cH - cN > 2.0f * delta)) {
-        // band of undecided latents: re-score with a compensated dot product
-        const float lo_b = cH - 2.0f * delta, hi_b = cN + 2.0f * delta;
-        uint64_t Um[RM], Cm[RM];
-#pragma unroll
-        for (int i = 0; i < RM; ++i) {
-          const bool valid = (i < R) && (64 * i + lane < H);
-          Um[i] = ballot64(valid && sc[i] >= lo_b && sc[i] <= hi_b);
-          Cm[i] = ballot64(valid && sc[i] > hi_b);
-        }
-        const float* yrow = Y + n * D;
-#pragma unroll
-        for (int i = 0; i < RM; ++i) {
-          uint64_t m = Um[i];
-          while (m) {
-            const int l2 = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1ull;
-            const int h = 64 * i + l2;
-            const float* prow = Pt32 + (int64_t)h * Dp;
-            float s = 0.0f, c = 0.0f;
-            for (int d = lane; d < D; d += 64) {
-              float p, e, s2, e2;
-              two_prod(yrow[d], prow[d], p, e);
-              two_sum(s, p, s2, e2);
-              s = s2;
-              c += e2 + e;
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-              const float so = __shfl_xor(s, o, 64), co = __shfl_xor(c, o, 64);
-              float s2, e2;
-              two_sum(s, so, s2, e2);
-              s = s2;
-              c = c + co + e2;
-            }
-            const float sg = (score_abs && s < 0.0f) ? -1.0f : 1.0f;
-            const float rr = (sg * s - hn_hi[h]) + (sg * c - hn_lo[h]);
-            if (lane == l2) {
-              sc[i] = rr;
-              b[i] = s + c;
-              key[i] = f2key(rr);
-            }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < RM; ++i) {
-          if (!((Um[i] >> lane) & 1ull)) key[i] = ((Cm[i] >> lane) & 1ull) ? 0xFFFFFFFFu : 0u;
-        }
-        radix_select<RM>(key, R, Hp, selm);
-        float uH = INFINITY, uN = -INFINITY;
-#pragma unroll
-        for (int i = 0; i < RM; ++i) {
-          if ((Um[i] >> lane) & 1ull) {
-            if ((selm[i] >> lane) & 1ull) uH = fminf(uH, sc[i]);
-            else uN = fmaxf(uN, sc[i]);
-          }
-        }
-        uH = wave_min(uH);
-        uN = wave_max(uN);
-        flag = (uH - uN <= 1e-6f * fmaxf(1.0f, fabsf(uH))) ? 1 : 0;
-      }
+      exact_select_point<RM>(Bs + r * Hs, lane, R, H, Hp, score_abs, true, sl.thr[r],
+                             sl.thrN[r], delta, Y + n * D, D, Dp, Pt32, hn_hi, hn_lo,
+                             sel + n * Hp, bc + n * Hp, flagged ? flagged + n : nullptr);
+      if (lane == 0) yy_out[n] = yyS[r];
     }
-    int base = 0;
-#pragma unroll
-    for (int i = 0; i < RM; ++i) {
-      const uint64_t m = selm[i];
-      if ((m >> lane) & 1ull) {
-        const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-        sel[n * Hp + pos] = 64 * i + lane;
-        bc[n * Hp + pos] = b[i];
-      }
-      base += __popcll(m);
-    }
-    if (lane == 0) {
-      yy_out[n] = yyS[r];
-      if (flagged) flagged[n] = flag;
+  } else {
+    for (int r = wave; r < TM; r += 4) {
+      const int64_t n = n0 + r;
+      if (n >= N) break;
+      const float ynorm = sqrtf(yyS[r]);
+      const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+      exact_select_point<RM>(Bs + r * Hs, lane, R, H, Hp, score_abs, false, 0.0f, 0.0f, delta,
+                             Y + n * D, D, Dp, Pt32, hn_hi, hn_lo, sel + n * Hp, bc + n * Hp,
+                             flagged ? flagged + n : nullptr);
+      if (lane == 0) yy_out[n] = yyS[r];
     }
   }
   if (scal && threadIdx.x == 0) {  // [2] sum ||y||^2, [4] number of points
@@ -361,11 +702,11 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
   }
 }
 
-template <int PREC, int TM, int RM>
+template <int PREC, int TM, int RM, bool FAST>
 static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int Hp,
                             int score_abs, float kappa, const Prepared& p, const Scratch& s,
                             uint8_t* flagged, double* scal, size_t lds, hipStream_t st) {
-  auto kern = k_project_select<PREC, TM, RM>;
+  auto kern = k_project_select<PREC, TM, RM, FAST>;
   static size_t configured = 0;
   if (lds > configured) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -374,31 +715,34 @@ static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int
     configured = lds;
   }
   const int64_t nblk = (N + TM - 1) / TM;
+  const int tile_bytes = (int)(lds - (size_t)round_up(H, 64) * 8);
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(256), lds, st, Y, N, D, Dp, H, p.Pt32,
                      p.Pt_hi, p.Pt_lo, p.hn_hi, p.hn_lo, p.pnorm, Hp, score_abs, kappa, s.sel,
-                     s.bc, s.yy, flagged, scal);
+                     s.bc, s.yy, flagged, scal, tile_bytes);
   return hipGetLastError();
 }
 
-// Points per workgroup: the score tile (TM x H) and the Y tile (TM x D) share
-// at most ~80 KB of LDS so that two workgroups fit on a CU.
-static int choose_tm(int Dp, int H, int prec) {
-  const int Hpad = round_up(H, 64);
-  int tm = Hpad <= 256 ? 64 : (Hpad <= 512 ? 32 : 16);
-  auto bytes = [&](int t) {
-    size_t yrow = (prec == PROSPER_FP32) ? (size_t)(Dp + 4) * 4 : (size_t)(Dp + 8) * 4;
-    size_t brow = (size_t)(Hpad + 4) * 4;
-    return (size_t)t * (yrow > brow ? yrow : brow);
-  };
-  while (tm > 16 && bytes(tm) > 80 * 1024) tm /= 2;
-  return tm;
-}
-
+// Dynamic LDS: the score tile (TM x (Hpad + 1)) and the Y tile share one
+// region, followed by the half norms of the latents.
 size_t project_lds_bytes(int Dp, int H, int prec, int tm) {
   const int Hpad = round_up(H, 64);
   size_t yrow = (prec == PROSPER_FP32) ? (size_t)(Dp + 4) * 4 : (size_t)(Dp + 8) * 4;
-  size_t brow = (size_t)(Hpad + 4) * 4;
-  return (size_t)tm * (yrow > brow ? yrow : brow);
+  size_t brow = (size_t)(Hpad + 1) * 4;
+  return round_up((int)((size_t)tm * (yrow > brow ? yrow : brow)), 16) + (size_t)Hpad * 8;
+}
+
+static size_t static_lds_bytes(int tm) {
+  const size_t sel = tm == 64 ? sizeof(SelLds<64>) : (tm == 32 ? sizeof(SelLds<32>) : sizeof(SelLds<16>));
+  return sel + (size_t)tm * 12 + 64;
+}
+
+// Two workgroups per CU: dynamic + static LDS of one within 80 KB.
+static int choose_tm(int Dp, int H, int prec) {
+  const int Hpad = round_up(H, 64);
+  int tm = Hpad <= 256 ? 64 : (Hpad <= 512 ? 32 : 16);
+  while (tm > 16 && project_lds_bytes(Dp, H, prec, tm) + static_lds_bytes(tm) > 80 * 1024)
+    tm /= 2;
+  return tm;
 }
 
 hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N, int D, int Dp,
@@ -406,16 +750,26 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
                                  uint8_t* flagged, double* scal, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   const int score_abs = (model == PROSPER_TSC) ? 1 : 0;
+  // Bound on |computed b - exact b| per unit of ||y|| ||P_h|| (Cauchy-Schwarz
+  // on sum |y_d P_hd|).  FP32: every product rounded once, at most D + 1
+  // roundings along the FP32 accumulation (padding adds exact zeros).  BF16
+  // head/tail split: head*head, head*tail and tail*head are exact in FP32;
+  // the dropped tail*tail and the two split remainders are each at most
+  // 2^-16 |y_d P_hd|, and 3 D + 1 accumulations follow.  1% slack on both.
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float kappa = (prec == PROSPER_FP32)
-                          ? (float)(2.0 * Dp * u)
-                          : (float)(2.0 * (1.0 / 65536.0 + 3.0 * Dp * u));
+                          ? (float)(1.01 * (D + 2) * u)
+                          : (float)(1.01 * (3.0 / 65536.0 + (3.0 * D + 2) * u));
   const int tm = choose_tm(Dp, H, prec);
   const size_t lds = project_lds_bytes(Dp, H, prec, tm);
   const int Hpad = round_up(H, 64);
   const bool small = Hpad <= 256;
-#define PS_CASE(P, T, R) \
-  return launch_ps<P, T, R>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged, scal, lds, st)
+  const bool fast = Hp <= FAST_HP && Hp < H;
+#define PS_CASE(P, T, R)                                                                       \
+  return fast ? launch_ps<P, T, R, true>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged,  \
+                                         scal, lds, st)                                        \
+              : launch_ps<P, T, R, false>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged, \
+                                          scal, lds, st)
   if (prec == PROSPER_FP32) {
     if (small) {
       if (tm == 64) PS_CASE(PROSPER_FP32, 64, 4);

@@ -18,20 +18,10 @@
 //   sum_s 2^(lj-m) s_i s_j   = sum over nodes ending in j containing i of T(node)
 #pragma once
 
-#include <type_traits>
-
 #include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
 namespace prosper {
-
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 

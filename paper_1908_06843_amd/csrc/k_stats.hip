@@ -113,24 +113,30 @@ __global__ __launch_bounds__(256) void k_stats_A(const float* __restrict__ Y, in
   }
 }
 
-// A partials on MFMA (D, H <= 256): A = Y^T S over a tile of 64 points, with
+// A partials on MFMA (D, H <= 256): A = Y^T S over tiles of 64 points, with
 // S the points x H matrix holding <s_j> at column sel_j (at most H' non-zeros
 // per row).  The S tile is scattered into LDS from (sel, <s>) and undone
 // after use; both operands are split into BF16 head + tail and three
 // products are summed (head*head + head*tail + tail*head) with FP32
 // accumulation, which keeps the relative product error below 2^-16.
-// Persistent workgroups keep their whole D x H partial in accumulator
-// registers (wave w: row tiles w, w+4, w+8, w+12 x 16 column tiles) and
-// store it once at the end.
+// Persistent workgroups (one wave per SIMD) keep their whole D x H partial
+// in accumulator registers (wave w: row tiles w, w+4, w+8, w+12 x 16 column
+// tiles) and store it once at the end.  Y rows are read whole (one 1 KB
+// row per wave load) into an FP32 row-major tile; the transpose the MFMA
+// needs (eight consecutive points of one pixel per lane) happens on the LDS
+// reads.  The next tile's Y, sel and <s> are loaded into registers while the
+// current tile is multiplied.
 //   A operand (16 x 32): Y^T[d][pt], lane l: d = 16 rt + l % 16, points 8 (l / 16) .. + 8
 //   B operand (32 x 16): S^T[h][pt],  lane l: h = 16 ct + l % 16, same points
 static constexpr int AT_PTS = 64;         // points per tile (two k-steps of 32)
-static constexpr int AT_LD = AT_PTS + 8;  // bf16 row stride of the transposed tiles
+static constexpr int AT_LD = AT_PTS + 8;  // bf16 row stride of the transposed S tile
+static constexpr int AT_YS = 258;         // float row stride of the Y tile
 
+template <int SELN>  // (sel, <s>) entries per thread and tile: 64 H' <= 256 SELN
 __global__ __launch_bounds__(256, 1) void k_stats_A_mfma(
     const float* __restrict__ Y, int64_t N, int D, int H, int Hp, const int32_t* __restrict__ sel,
     const float* __restrict__ s_mean, float* __restrict__ partA) {
-  __shared__ __align__(16) bf16 Yh[256 * AT_LD], Yl[256 * AT_LD];
+  __shared__ __align__(16) float Yf[AT_PTS * AT_YS];
   __shared__ __align__(16) bf16 Sh[256 * AT_LD], Sl[256 * AT_LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q = lane >> 4, r16 = lane & 15;
@@ -140,61 +146,100 @@ __global__ __launch_bounds__(256, 1) void k_stats_A_mfma(
     Sh[e] = (bf16)0.0f;
     Sl[e] = (bf16)0.0f;
   }
+  for (int e = tid; e < AT_PTS * AT_YS; e += 256) Yf[e] = 0.0f;
   f32x4 acc[4][16];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 16; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+
+  // thread -> float4 column c4 = lane of rows wave + 4 j (j < 16)
+  const bool vec = (D & 3) == 0;
+  const int c4 = lane, dd = 4 * c4;
+  float4 yv[16];
+  int sv_h[SELN];
+  float sv_m[SELN];
+  auto fetch = [&](int64_t t) {
     const int64_t n0 = t * AT_PTS;
-    const int np = (int)min((int64_t)AT_PTS, N - n0);
-    __syncthreads();  // previous tile's MFMA reads are done
-    // Y^T tile: thread handles pixel d = tid (rows of 64 points)
-    if (tid < Dt * 16) {
-      const int d = tid;
-#pragma unroll 8
-      for (int p = 0; p < AT_PTS; ++p) {
-        const float v = (p < np && d < D) ? Y[(n0 + p) * D + d] : 0.0f;
-        const bf16 hi = (bf16)v;
-        Yh[d * AT_LD + p] = hi;
-        Yl[d * AT_LD + p] = (bf16)(v - (float)hi);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t n = n0 + wave + 4 * j;
+      const bool nok = n < N;
+      const float* yr = Y + (nok ? n : N - 1) * D;
+      if (vec) {
+        const float4 x = *reinterpret_cast<const float4*>(yr + (dd < D ? dd : 0));
+        yv[j] = (nok && dd < D) ? x : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        float e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float x = yr[min(dd + k, D - 1)];
+          e[k] = (nok && dd + k < D) ? x : 0.f;
+        }
+        yv[j] = make_float4(e[0], e[1], e[2], e[3]);
       }
     }
-    // S^T tile: scatter <s_j> of point p into row sel_j
-    for (int e = tid; e < np * Hp; e += 256) {
-      const int p = e / Hp;
-      const int h = sel[(n0 + p) * Hp + (e - p * Hp)];
-      const float v = s_mean[(n0 + p) * Hp + (e - p * Hp)];
-      const bf16 hi = (bf16)v;
-      Sh[h * AT_LD + p] = hi;
-      Sl[h * AT_LD + p] = (bf16)(v - (float)hi);
+    const int64_t nent = min((int64_t)AT_PTS, N - n0) * Hp;
+#pragma unroll
+    for (int u = 0; u < SELN; ++u) {
+      const int64_t e = tid + 256 * u;
+      const int64_t ec = e < nent ? e : 0;
+      const int h = sel[n0 * Hp + ec];
+      const float m = s_mean[n0 * Hp + ec];
+      sv_h[u] = e < nent ? h : -1;
+      sv_m[u] = m;
+    }
+  };
+  if ((int64_t)blockIdx.x < ntiles) fetch(blockIdx.x);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // LDS is free: the previous tile's products and undo are complete
+    if (dd < D) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        float2* dst = reinterpret_cast<float2*>(&Yf[(wave + 4 * j) * AT_YS + dd]);
+        dst[0] = make_float2(yv[j].x, yv[j].y);
+        dst[1] = make_float2(yv[j].z, yv[j].w);
+      }
+    }
+    int cur_h[SELN];
+#pragma unroll
+    for (int u = 0; u < SELN; ++u) {
+      cur_h[u] = sv_h[u];
+      if (cur_h[u] >= 0) {
+        const int pt = (tid + 256 * u) / Hp;
+        const float v = sv_m[u];
+        const bf16 hh = (bf16)v;
+        Sh[cur_h[u] * AT_LD + pt] = hh;
+        Sl[cur_h[u] * AT_LD + pt] = (bf16)(v - (float)hh);
+      }
     }
     __syncthreads();
+    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);
 #pragma unroll
     for (int ks = 0; ks < AT_PTS / 32; ++ks) {
-      bf16x8 bh[16], bl[16];
-#pragma unroll
-      for (int ct = 0; ct < 16; ++ct) {
-        if (ct < Ht) {
-          const int o = (16 * ct + r16) * AT_LD + 32 * ks + 8 * q;
-          bh[ct] = *reinterpret_cast<const bf16x8*>(&Sh[o]);
-          bl[ct] = *reinterpret_cast<const bf16x8*>(&Sl[o]);
-        }
-      }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int rt = wave + 4 * a;
         if (rt < Dt) {
-          const int o = (16 * rt + r16) * AT_LD + 32 * ks + 8 * q;
-          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Yh[o]);
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(&Yl[o]);
+          bf16x8 ah, al;
+          const float* col = &Yf[(32 * ks + 8 * q) * AT_YS + 16 * rt + r16];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float v = col[e * AT_YS];
+            const bf16 hv = (bf16)v;
+            ah[e] = hv;
+            al[e] = (bf16)(v - (float)hv);
+          }
 #pragma unroll
           for (int ct = 0; ct < 16; ++ct) {
             if (ct < Ht) {
+              const int ob = (16 * ct + r16) * AT_LD + 32 * ks + 8 * q;
+              const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Sh[ob]);
+              const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Sl[ob]);
               f32x4& c = acc[a][ct];
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
             }
           }
         }
@@ -202,12 +247,15 @@ __global__ __launch_bounds__(256, 1) void k_stats_A_mfma(
     }
     __syncthreads();
     // undo the scatter so the S tile is zero again
-    for (int e = tid; e < np * Hp; e += 256) {
-      const int p = e / Hp;
-      const int h = sel[(n0 + p) * Hp + (e - p * Hp)];
-      Sh[h * AT_LD + p] = (bf16)0.0f;
-      Sl[h * AT_LD + p] = (bf16)0.0f;
+#pragma unroll
+    for (int u = 0; u < SELN; ++u) {
+      if (cur_h[u] >= 0) {
+        const int pt = (tid + 256 * u) / Hp;
+        Sh[cur_h[u] * AT_LD + pt] = (bf16)0.0f;
+        Sl[cur_h[u] * AT_LD + pt] = (bf16)0.0f;
+      }
     }
+    __syncthreads();
   }
   float* out = partA + (int64_t)blockIdx.x * D * H;
 #pragma unroll
@@ -388,8 +436,12 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
   if (mfmaA) {
     const int64_t ntiles = (N + AT_PTS - 1) / AT_PTS;
     const int nwg = (int)(ntiles < pl.mfma_wgs ? ntiles : pl.mfma_wgs);
-    hipLaunchKernelGGL(k_stats_A_mfma, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, H, Hp,
-                       s.sel, s.s_mean, s.partA);
+    if (Hp <= 16)
+      hipLaunchKernelGGL(k_stats_A_mfma<4>, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, H, Hp,
+                         s.sel, s.s_mean, s.partA);
+    else
+      hipLaunchKernelGGL(k_stats_A_mfma<8>, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, H, Hp,
+                         s.sel, s.s_mean, s.partA);
     const int64_t n = (int64_t)D * H;
     hipLaunchKernelGGL(k_stats_A_reduce, dim3((unsigned)((n / 4 + 256) / 256)), dim3(256), 0, st,
                        D, H, nwg, s.partA, A);

@@ -70,6 +70,10 @@ struct Scratch {
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Row length of the transposed projection matrix and of the staged Y tiles:
+// the projection kernel reads 64 consecutive depths of a row per step.
+inline int padded_depth(int D) { return round_up(D, 64); }
+
 // Bump allocator over one device allocation (256-byte aligned pieces).
 struct Carve {
   char* base;

@@ -321,7 +321,7 @@ prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_devi
   s->model = model;
   s->D = D;
   s->H = H;
-  s->Dp = round_up(D, 32);
+  s->Dp = padded_depth(D);
   s->prec = precision;
   s->pi = pi;
   s->sigma = sigma;
