@@ -202,6 +202,103 @@ def serving_bench(np, api, n_req, prec):
             "patches_per_s": patches / load_s}
 
 
+def project_select_work(N, D, H, Hp):
+    """Algorithmic work of one projection + preselection launch: MFMA flops
+    2 D H per point (b = W^T y), HBM bytes: y once (4 D) plus the outputs
+    (sel and b of the H' candidates, ||y||^2, the flag)."""
+    return 2.0 * N * D * H, N * (4.0 * D + 8.0 * Hp + 4.0 + 1.0)
+
+
+def roofline(kernel, per_launch_s, N, wl):
+    """Roofline entry for one kernel group: the bound is the resource whose
+    time at peak is largest for the kernel's algorithmic work."""
+    if kernel == "project_select":
+        flops, nbytes = project_select_work(N, wl.D, wl.H, wl.Hprime)
+        t_mfma = flops / (MFMA_PEAK_TFLOPS["bf16"] * 1e12)
+        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+        if t_hbm >= t_mfma:
+            roof = {"bound": "hbm", "achieved": nbytes / per_launch_s / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            roof = {"bound": "mfma", "achieved": flops / per_launch_s / 1e12,
+                    "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s"}
+    elif kernel == "states_lin":
+        work = N * state_walk_ops(wl.Hprime, wl.gamma)
+        roof = {"bound": "alu", "achieved": work / per_launch_s / 1e12,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
+    else:
+        nbytes = N * wl.D * 4.0
+        roof = {"bound": "hbm", "achieved": nbytes / per_launch_s / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(kernel)
+    roof["kernel"] = kernel
+    roof["kernel_us"] = per_launch_s * 1e6
+    return roof
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_project_select_bsc256.md")
+KERNEL_SOURCES = {"project_select": ["paper_1908_06843_amd/csrc/k_project.hip",
+                                     "paper_1908_06843_amd/csrc/dev_common.hpp",
+                                     "paper_1908_06843_amd/csrc/prosper_internal.hpp"]}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel's sources changed since it was taken."""
+    if kernel not in KERNEL_SOURCES or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    try:
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pmc_pass():
+    """Short run for hardware-counter passes: one device copy of a known size
+    (the scale reference for the byte counters), then two BF16 E-steps with
+    statistics at BSC scale."""
+    import torch
+    import synth
+    from paper_1908_06843_amd import api
+    wl = synth.WORKLOADS["bsc256"]
+    Y, _, _, _ = synth.make_workload("bsc256")
+    W0, pi0, s0 = synth.initial_params(wl, Y)
+    dev = torch.device("cuda", 0)
+    Yd = torch.tensor(Y, device=dev)
+    Z = torch.empty_like(Yd)
+    Z.copy_(Yd)
+    torch.cuda.synchronize()
+    ctx = api.context(0)
+    Wd = torch.tensor(W0, device=dev)
+    acc = api.new_acc("bsc", wl.D, wl.H)
+    for _ in range(2):
+        api.zero_acc(acc)
+        api.estep(Yd, Wd, pi0, s0, Hprime=wl.Hprime, gamma=wl.gamma, precision="bf16", acc=acc,
+                  want=(), ctx=ctx)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_pass": "done", "copy_bytes": int(Yd.numel() * 4),
+                      "project_select_source_hash": kernel_source_hash("project_select")}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,11 +309,16 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="short run for rocprofv3 counter passes (no JSON metric line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    "the multi-GPU data-parallel path is a design, not a build"}))
         sys.exit(2)
+    if args.pmc_pass:
+        pmc_pass()
+        return
 
     import numpy as np
     import torch
@@ -260,28 +362,13 @@ def main():
             g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
             err[prec] = error_stats(g, ref)
 
-    # roofline of the dominant kernel group of the BF16 step
+    # roofline of the dominant kernel of the BF16 step, priced at its
+    # algorithmic work against the resource that binds that work
     prof = res["bf16"]["profile"]
     dom = max((k for k in prof if k != "mstep"), key=lambda k: prof[k]["ms"])
-    per_launch_ms = prof[dom]["ms"] / prof[dom]["launches"]
+    per_launch_s = prof[dom]["ms"] / prof[dom]["launches"] * 1e-3
     N = Y.shape[0]
-    if dom == "states_lin":
-        work = N * state_walk_ops(wl.Hprime, wl.gamma)
-        roof = {"bound": "alu", "achieved": work / (per_launch_ms * 1e-3) / 1e12,
-                "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
-    elif dom == "project_select":
-        work = 2.0 * N * wl.D * wl.H
-        roof = {"bound": "mfma", "achieved": work / (per_launch_ms * 1e-3) / 1e12,
-                "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s"}
-    else:
-        work = N * wl.D * 4.0
-        roof = {"bound": "hbm", "achieved": work / (per_launch_ms * 1e-3) / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["kernel_us"] = per_launch_ms * 1e3
-
+    roof = roofline(dom, per_launch_s, N, wl)
     serving = None
     if not args.no_serve:
         serving = {p: serving_bench(np, api, args.serve_requests, p) for p in ("bf16", "fp32")}

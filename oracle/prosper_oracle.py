@@ -33,8 +33,13 @@ Readings where the paper is silent (each listed in the design notes):
 
 Parity pins: see tests/test_oracle_*.py (brute force over all states with
 scipy's multivariate normal, closed forms at H = 1, MCA == BSC special cases,
-posterior invariants, textbook least squares, the EM monotonicity theorem,
-bars recovery).
+posterior invariants, textbook least squares, the MCA update as a cluster
+mean for single-cause posteriors, the EM monotonicity theorem, bars
+recovery).
+
+Parity unpinned: the MCA noise update's use of the old W (mstep, MCA
+branch) is a reading with nothing outside this file to check it against;
+its W update and everything else here is pinned.
 """
 from __future__ import annotations
 

@@ -374,6 +374,22 @@ def test_mca_mstep_responsibilities_sum():
     np.testing.assert_allclose(p["R"].sum(axis=1), 1 - q0, rtol=1e-12)
 
 
+def test_mca_mstep_single_cause_is_cluster_mean():
+    """With one cause per point (gamma = 1) and posteriors concentrated on the
+    generating cause (small sigma, well separated non-negative columns), the
+    MCA responsibilities are hard assignments and the W update is the mean
+    of the points assigned to each component (a k-means centroid step)."""
+    g = np.random.default_rng(17)
+    D, H, N = 9, 4, 80
+    W = np.abs(g.standard_normal((D, H))) * 3.0 + 0.5
+    lab = g.integers(0, H, N)
+    Y = W[:, lab].T + 0.05 * g.standard_normal((N, D))
+    est = O.estep("mca", Y, W, 0.3, 0.05, H, 1)
+    Wn, _, _ = O.mstep("mca", Y, W, est)
+    for h in range(H):
+        np.testing.assert_allclose(Wn[:, h], Y[lab == h].mean(axis=0), rtol=1e-9, atol=1e-9)
+
+
 # ---------------------------------------------------------------- EM
 def test_exact_em_free_energy_monotone_on_bars():
     Y, _, _, wl = synth.make_workload("bars", N=300)
