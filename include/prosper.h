@@ -63,8 +63,19 @@ typedef enum { PROSPER_BSC = 0, PROSPER_TSC = 1, PROSPER_MCA = 2 } prosper_model
  * runs in FP32; M-step solve and the sigma/pi reductions run in FP64. */
 typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1 } prosper_precision;
 
-/* Flags for prosper_args.flags (no flag is defined in this build; must be 0) */
+/* Flags for prosper_args.flags */
 #define PROSPER_FLAG_NONE          0u
+/* PROSPER_FLAG_FACTOR_B (BSC/TSC, accumulate = 1 only; EINVAL otherwise):
+ * this call completes the accumulation of acc for the next M-step.  After
+ * adding its own <s s^T> into acc->B, the library factors B (the Cholesky
+ * factor prosper_mstep needs, see there) in the context's workspace on a
+ * second stream, overlapped with the A statistics of the same call; the call
+ * still completes on `stream` only when the factor is done.  A following
+ * prosper_mstep on the same context with the same acc->B pointer, D, H and
+ * model reuses that factor and only solves.  Any later accumulating E-step,
+ * or any prosper_mstep, on the context discards it; the caller must not
+ * modify acc->B in between. */
+#define PROSPER_FLAG_FACTOR_B      1u
 
 /* Limits of this build */
 #define PROSPER_MAX_HPRIME   32
@@ -88,7 +99,7 @@ typedef struct {
     int32_t topk;           /* 0..PROSPER_MAX_TOPK most probable states per point;
                                topk <= |K| */
     int32_t accumulate;     /* 1: add the M-step sufficient statistics into acc */
-    uint32_t flags;         /* PROSPER_FLAG_NONE */
+    uint32_t flags;         /* PROSPER_FLAG_NONE or PROSPER_FLAG_FACTOR_B */
     int32_t reserved;
 } prosper_args;
 

@@ -28,6 +28,9 @@ class ProsperError(RuntimeError):
         self.status = status
 
 
+FLAG_FACTOR_B = 1  # PROSPER_FLAG_FACTOR_B
+
+
 class Args(C.Structure):
     _fields_ = [("model", C.c_int32), ("precision", C.c_int32), ("N", C.c_int64),
                 ("D", C.c_int32), ("H", C.c_int32), ("Hprime", C.c_int32),

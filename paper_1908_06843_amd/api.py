@@ -96,14 +96,17 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
           theta: Optional[torch.Tensor] = None,
           want: Sequence[str] = ("sel", "s_mean", "logL", "flagged"),
           out: Optional[Dict[str, torch.Tensor]] = None,
-          ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None
-          ) -> Dict[str, torch.Tensor]:
+          ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None,
+          factor_b: bool = False) -> Dict[str, torch.Tensor]:
     """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
 
     Returns the requested per-point outputs: sel (N x H' int32), s_mean
     (N x H'), logL (N), flagged (N uint8), top_mask / top_q (N x topk).
     `theta` (2 doubles on the device: pi, sigma) overrides pi and sigma.
     `out` may supply preallocated output tensors (same keys).
+    `factor_b` (with `acc`, BSC/TSC): this call completes the accumulation;
+    B is factored for the next `mstep` with the same acc, overlapped with the
+    A statistics (PROSPER_FLAG_FACTOR_B).
     """
     _dev_f32("Y", Y)
     _dev_f32("W", W)
@@ -142,7 +145,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     if acc is not None:
         accs = _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]))
     args = _lib.make_args(model, precision, N, D, H, Hprime, gamma, pi, sigma,
-                          _ptr(theta), topk, 1 if acc is not None else 0)
+                          _ptr(theta), topk, 1 if acc is not None else 0,
+                          _lib.FLAG_FACTOR_B if factor_b else 0)
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lib = _lib.load()
     _lib.check(lib.prosper_estep(ctx.handle, C.byref(args), _ptr(Y), _ptr(W), C.byref(po),

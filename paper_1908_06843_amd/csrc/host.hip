@@ -61,6 +61,12 @@ struct prosper_ctx {
   std::vector<std::tuple<const char*, hipEvent_t, hipEvent_t>> ev_pending;
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<std::string> prof_order;
+  // B factored ahead by an E-step (PROSPER_FLAG_FACTOR_B) on the side stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_b = nullptr, ev_f = nullptr;
+  bool factor_ready = false;
+  const float* factor_B = nullptr;
+  int factor_model = -1, factor_D = 0, factor_H = 0;
 };
 
 namespace {
@@ -217,8 +223,12 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "accumulate must be 0 or 1";
     return PROSPER_EINVAL;
   }
-  if (a->flags != 0u) {
+  if ((a->flags & ~PROSPER_FLAG_FACTOR_B) != 0u) {
     *msg = "unknown flag bits";
+    return PROSPER_EINVAL;
+  }
+  if ((a->flags & PROSPER_FLAG_FACTOR_B) && (!a->accumulate || a->model == PROSPER_MCA)) {
+    *msg = "PROSPER_FLAG_FACTOR_B needs accumulate = 1 and a linear model (BSC/TSC)";
     return PROSPER_EINVAL;
   }
   int64_t ns = 0;
@@ -359,7 +369,8 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
   int tree_blocks = 0;
   e = launch_states_lin(model, Hp, gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask,
                         top_q, topk, A != nullptr, B, scal, num_cu, &tree_blocks, s);
-  if (e == hipSuccess && A) e = launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, A, B, s);
+  if (e == hipSuccess && A)
+    e = launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, A, B, s, StatsHook(), 0);
   return e;
 }
 }  // namespace prosper
@@ -470,6 +481,9 @@ void prosper_ctx_destroy(prosper_ctx* c) {
   if (c->prep.p) hipFree(c->prep.p);
   if (c->scratch.p) hipFree(c->scratch.p);
   if (c->mwork.p) hipFree(c->mwork.p);
+  if (c->side) hipStreamDestroy(c->side);
+  if (c->ev_b) hipEventDestroy(c->ev_b);
+  if (c->ev_f) hipEventDestroy(c->ev_f);
   prof_collect(c);
   for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
   delete c;
@@ -558,6 +572,28 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   float* Aacc = a->accumulate ? acc->A : nullptr;
   int tree_blocks = 0;
   float* Bacc = a->accumulate ? acc->B : nullptr;
+  if (a->accumulate) c->factor_ready = false;
+  const bool factor_b = (a->flags & PROSPER_FLAG_FACTOR_B) != 0u;
+  if (factor_b) {
+    if (!c->side) {
+      e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_f, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(c, e, "side stream for the B factor");
+    }
+    e = ensure(c->mwork, mstep_workspace_bytes(model, D, H));
+    if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "M-step workspace allocation failed");
+  }
+  // after B is complete: fork its factorisation onto the side stream
+  auto after_B = [&](hipStream_t st) -> hipError_t {
+    hipError_t e2 = hipEventRecord(c->ev_b, st);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(c->side, c->ev_b, 0);
+    if (e2 == hipSuccess)
+      e2 = timed(c, "mstep_factor", c->side,
+                 [&] { return launch_mstep_factor(model, D, H, acc->B, c->mwork.p, c->side); });
+    if (e2 == hipSuccess) e2 = hipEventRecord(c->ev_f, c->side);
+    return e2;
+  };
   double* scal = a->accumulate ? acc->scal : nullptr;
   if (e == hipSuccess)
     e = timed(c, "project_select", s, [&] {
@@ -574,9 +610,18 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
     });
   if (e == hipSuccess && Aacc && model != PROSPER_MCA)
     e = timed(c, "stats", s, [&] {
-      return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s);
+      return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s,
+                          factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 16 : 0);
     });
+  if (e == hipSuccess && factor_b) e = hipStreamWaitEvent(s, c->ev_f, 0);
   if (e != hipSuccess) return hip_fail(c, e, "E-step launch");
+  if (factor_b) {
+    c->factor_ready = true;
+    c->factor_B = acc->B;
+    c->factor_model = model;
+    c->factor_D = D;
+    c->factor_H = H;
+  }
   return PROSPER_OK;
 }
 
@@ -595,7 +640,13 @@ prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prospe
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   e = ensure(c->mwork, mstep_workspace_bytes(a->model, a->D, a->H));
   if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "M-step workspace allocation failed");
+  const bool reuse = c->factor_ready && c->factor_B == acc->B && c->factor_model == a->model &&
+                     c->factor_D == a->D && c->factor_H == a->H;
+  c->factor_ready = false;
   e = timed(c, "mstep", s, [&] {
+    if (reuse)
+      return launch_mstep_solve(a->model, a->D, a->H, acc->A, acc->B, acc->scal, W_old, W_new,
+                                theta_new, c->mwork.p, s);
     return launch_mstep(a->model, a->D, a->H, acc->A, acc->B, acc->scal, W_old, W_new, theta_new,
                         c->mwork.p, s);
   });

@@ -447,22 +447,17 @@ static void launch_solve(int D, int H, const float* A, const float* B, const Mst
                      w.M, w.invd, w.hdr, W_old, W_new, w.trp);
 }
 
-hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
-                        const double* scal, const float* W_old, float* W_new,
-                        double* theta_new, void* work, hipStream_t st) {
-  if (model == PROSPER_MCA) {
-    const int64_t n = (int64_t)D * H;
-    hipLaunchKernelGGL(k_mstep_mca, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, H, A,
-                       B, W_old, W_new);
-    hipLaunchKernelGGL(k_mstep_scalars_mca, dim3(1), dim3(64), 0, st, D, H, scal, theta_new);
-    return hipGetLastError();
-  }
+hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* work,
+                               hipStream_t st) {
+  if (model == PROSPER_MCA) return hipSuccess;
   if (H > 16 * 64) return hipErrorInvalidValue;
   const MstepWork w = carve_mstep(work, D, H);
   hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(1024), 0, st, H, B, w.hdr);
   const int64_t HH = (int64_t)H * H;
-  int64_t lb = (HH + 255) / 256;
-  if (lb > 2048) lb = 2048;
+  // few workgroups: when B is factored beside the A statistics only a few
+  // CUs are free
+  int64_t lb = (HH + 2047) / 2048;
+  if (lb > 16) lb = 16;
   hipLaunchKernelGGL(k_ms_load, dim3((unsigned)lb), dim3(256), 0, st, H, B, w.hdr, w.M);
   for (int kb = 0; kb < H; kb += NB) {
     const int nb = (H - kb < NB) ? H - kb : NB;
@@ -475,6 +470,21 @@ hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
                          w.M);
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_mstep_solve(int model, int D, int H, const float* A, const float* B,
+                              const double* scal, const float* W_old, float* W_new,
+                              double* theta_new, void* work, hipStream_t st) {
+  if (model == PROSPER_MCA) {
+    const int64_t n = (int64_t)D * H;
+    hipLaunchKernelGGL(k_mstep_mca, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, H, A,
+                       B, W_old, W_new);
+    hipLaunchKernelGGL(k_mstep_scalars_mca, dim3(1), dim3(64), 0, st, D, H, scal, theta_new);
+    return hipGetLastError();
+  }
+  if (H > 16 * 64) return hipErrorInvalidValue;
+  const MstepWork w = carve_mstep(work, D, H);
   if (H <= 64) launch_solve<1>(D, H, A, B, w, W_old, W_new, st);
   else if (H <= 128) launch_solve<2>(D, H, A, B, w, W_old, W_new, st);
   else if (H <= 256) launch_solve<4>(D, H, A, B, w, W_old, W_new, st);
@@ -482,6 +492,14 @@ hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
   else launch_solve<16>(D, H, A, B, w, W_old, W_new, st);
   hipLaunchKernelGGL(k_ms_scalars_lin, dim3(1), dim3(256), 0, st, D, H, scal, w.trp, theta_new);
   return hipGetLastError();
+}
+
+hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
+                        const double* scal, const float* W_old, float* W_new,
+                        double* theta_new, void* work, hipStream_t st) {
+  hipError_t e = launch_mstep_factor(model, D, H, B, work, st);
+  if (e != hipSuccess) return e;
+  return launch_mstep_solve(model, D, H, A, B, scal, W_old, W_new, theta_new, work, st);
 }
 
 }  // namespace prosper

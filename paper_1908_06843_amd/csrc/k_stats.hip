@@ -426,16 +426,53 @@ bool stats_a_mfma_ok(int D, int H) { return D <= 256 && H <= 256; }
 int stats_bslice_count(int H) { return bslice_count(H); }
 
 // B partials: either ngB = tree_blocks single-slice partials written by the
-// training state walk (ss == NULL), or formed here from pair-major ss.
+// training state walk (ss == NULL), or formed here from pair-major ss.  On
+// the MFMA path B is completed first and `after_B` runs before the A
+// statistics; reserve_cu CUs are then left out of the persistent A grid so
+// that work forked by the hook finds room.
 hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
                         const StatsPlan& pl, int tree_blocks, float* A, float* B,
-                        hipStream_t st) {
+                        hipStream_t st, const StatsHook& after_B, int reserve_cu) {
   if (N <= 0) return hipSuccess;
   const size_t ldsA = (size_t)H * (pl.DS + 1) * 4;
   const bool mfmaA = stats_a_mfma_ok(D, H);
+  auto reduce_B_and_A = [&](bool with_A) -> hipError_t {
+    int ngB = tree_blocks, nB = 1;
+    if (s.ss) {
+      const size_t ldsB = (size_t)BSLICE_MAX * 4;
+      static size_t configured = 0;
+      if (ldsB > configured) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_stats_B),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsB);
+        if (e != hipSuccess) return e;
+        configured = ldsB;
+      }
+      hipLaunchKernelGGL(k_stats_B, dim3((unsigned)(pl.ngroups * pl.nB)), dim3(256), ldsB, st, N,
+                         H, Hp, s.sel, s.ss, pl.nB, pl.ppg, s.partB);
+      ngB = pl.ngroups;
+      nB = pl.nB;
+    }
+    SliceRows rows;
+    for (int b = 0; b <= STATS_MAX_BSLICES; ++b) rows.r0[b] = H;
+    for (int b = 0; b < nB; ++b) {
+      int r0, r1;
+      bslice_bounds(H, b, &r0, &r1);
+      rows.r0[b] = r0;
+    }
+    const int64_t tot = (int64_t)D * H + (int64_t)H * H;
+    hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D,
+                       H, pl.DS, pl.nA, nB, rows, with_A ? pl.ngroups : 0, ngB, s.partA, s.partB,
+                       with_A ? A : nullptr, B);
+    return hipGetLastError();
+  };
   if (mfmaA) {
+    hipError_t e = reduce_B_and_A(false);
+    if (e == hipSuccess && after_B) e = after_B(st);
+    if (e != hipSuccess) return e;
     const int64_t ntiles = (N + AT_PTS - 1) / AT_PTS;
-    const int nwg = (int)(ntiles < pl.mfma_wgs ? ntiles : pl.mfma_wgs);
+    int cap = pl.mfma_wgs - reserve_cu;
+    if (cap < 1) cap = 1;
+    const int nwg = (int)(ntiles < cap ? ntiles : cap);
     if (Hp <= 16)
       hipLaunchKernelGGL(k_stats_A_mfma<4>, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, H, Hp,
                          s.sel, s.s_mean, s.partA);
@@ -445,51 +482,27 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
     const int64_t n = (int64_t)D * H;
     hipLaunchKernelGGL(k_stats_A_reduce, dim3((unsigned)((n / 4 + 256) / 256)), dim3(256), 0, st,
                        D, H, nwg, s.partA, A);
-  } else {
-    static size_t configured[2] = {0, 0};
-    const int which = Hp <= 16 ? 0 : 1;
-    const void* kern = which == 0 ? reinterpret_cast<const void*>(k_stats_A<16>)
-                                  : reinterpret_cast<const void*>(k_stats_A<32>);
-    if (ldsA > configured[which]) {
-      hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsA);
-      if (e != hipSuccess) return e;
-      configured[which] = ldsA;
-    }
-    const dim3 g((unsigned)(pl.ngroups * pl.nA));
-    if (which == 0)
-      hipLaunchKernelGGL(k_stats_A<16>, g, dim3(256), ldsA, st, Y, N, D, H, Hp, s.sel, s.s_mean,
-                         pl.DS, pl.nA, pl.ppg, s.partA);
-    else
-      hipLaunchKernelGGL(k_stats_A<32>, g, dim3(256), ldsA, st, Y, N, D, H, Hp, s.sel, s.s_mean,
-                         pl.DS, pl.nA, pl.ppg, s.partA);
+    return hipGetLastError();
   }
-  int ngB = tree_blocks, nB = 1;
-  if (s.ss) {
-    const size_t ldsB = (size_t)BSLICE_MAX * 4;
-    static size_t configured = 0;
-    if (ldsB > configured) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_stats_B),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsB);
-      if (e != hipSuccess) return e;
-      configured = ldsB;
-    }
-    hipLaunchKernelGGL(k_stats_B, dim3((unsigned)(pl.ngroups * pl.nB)), dim3(256), ldsB, st, N, H,
-                       Hp, s.sel, s.ss, pl.nB, pl.ppg, s.partB);
-    ngB = pl.ngroups;
-    nB = pl.nB;
+  static size_t configured[2] = {0, 0};
+  const int which = Hp <= 16 ? 0 : 1;
+  const void* kern = which == 0 ? reinterpret_cast<const void*>(k_stats_A<16>)
+                                : reinterpret_cast<const void*>(k_stats_A<32>);
+  if (ldsA > configured[which]) {
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsA);
+    if (e != hipSuccess) return e;
+    configured[which] = ldsA;
   }
-  SliceRows rows;
-  for (int b = 0; b <= STATS_MAX_BSLICES; ++b) rows.r0[b] = H;
-  for (int b = 0; b < nB; ++b) {
-    int r0, r1;
-    bslice_bounds(H, b, &r0, &r1);
-    rows.r0[b] = r0;
-  }
-  const int64_t tot = (int64_t)D * H + (int64_t)H * H;
-  hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, H,
-                     pl.DS, pl.nA, nB, rows, mfmaA ? 0 : pl.ngroups, ngB, s.partA, s.partB,
-                     mfmaA ? nullptr : A, B);
-  return hipGetLastError();
+  const dim3 g((unsigned)(pl.ngroups * pl.nA));
+  if (which == 0)
+    hipLaunchKernelGGL(k_stats_A<16>, g, dim3(256), ldsA, st, Y, N, D, H, Hp, s.sel, s.s_mean,
+                       pl.DS, pl.nA, pl.ppg, s.partA);
+  else
+    hipLaunchKernelGGL(k_stats_A<32>, g, dim3(256), ldsA, st, Y, N, D, H, Hp, s.sel, s.s_mean,
+                       pl.DS, pl.nA, pl.ppg, s.partA);
+  hipError_t e = reduce_B_and_A(true);
+  if (e == hipSuccess && after_B) e = after_B(st);
+  return e;
 }
 
 }  // namespace prosper

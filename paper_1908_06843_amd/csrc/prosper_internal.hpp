@@ -2,6 +2,8 @@
 // the host-side launchers of every kernel.  Not part of the public ABI.
 #pragma once
 
+#include <functional>
+
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
@@ -125,14 +127,24 @@ hipError_t launch_states_max(int Hp, int gamma, int64_t N, int D, int Dp, int H,
 int stats_bslice_floats();
 bool stats_a_mfma_ok(int D, int H);
 int stats_bslice_count(int H);
+// Called on the E-step stream once B holds every contribution of the call
+// (before the A statistics are formed), to fork work that needs only B.
+typedef std::function<hipError_t(hipStream_t)> StatsHook;
 hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
-                        const StatsPlan& pl, int tree_blocks, float* A, float* B,
-                        hipStream_t st);
+                        const StatsPlan& pl, int tree_blocks, float* A, float* B, hipStream_t st,
+                        const StatsHook& after_B, int reserve_cu);
 // M-step.
 size_t mstep_workspace_bytes(int model, int D, int H);
 hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
                         const double* scal, const float* W_old, float* W_new,
                         double* theta_new, void* work, hipStream_t st);
+// The two halves of launch_mstep for BSC/TSC: factorisation of B into the
+// workspace, and the solve + parameter update that uses it.
+hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* work,
+                               hipStream_t st);
+hipError_t launch_mstep_solve(int model, int D, int H, const float* A, const float* B,
+                              const double* scal, const float* W_old, float* W_new,
+                              double* theta_new, void* work, hipStream_t st);
 
 // Projection/preselection + state walk + A accumulation (after k_prep).
 hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int D, int H, int Hp,

@@ -95,12 +95,20 @@ def test_validate_accepts_good_args():
                                  dict(gamma=-1), dict(gamma=5), dict(pi=0.0), dict(pi=1.0),
                                  dict(pi=float("nan")), dict(sigma=0.0), dict(sigma=-1.0),
                                  dict(sigma=float("inf")), dict(topk=9), dict(topk=-1),
-                                 dict(accumulate=2), dict(flags=1),
+                                 dict(accumulate=2), dict(flags=2), dict(flags=1),
                                  dict(Hprime=2, gamma=1, topk=4)])
 def test_validate_rejects_each_bad_field(bad):
     a = good_args(**bad)
     assert _lib.validate(a) == -1
     assert len(_lib.last_error()) > 0
+
+
+def test_factor_b_flag_needs_accumulating_linear_model():
+    assert _lib.validate(good_args(accumulate=1, flags=_lib.FLAG_FACTOR_B)) == 0
+    assert _lib.validate(good_args(accumulate=0, flags=_lib.FLAG_FACTOR_B)) == -1
+    a = good_args(accumulate=1, flags=_lib.FLAG_FACTOR_B)
+    a.model = 2  # MCA
+    assert _lib.validate(a) == -1
 
 
 def test_validate_rejects_unknown_enums():

@@ -87,6 +87,45 @@ def test_mstep_in_place_and_inactive_columns():
     assert rel(Wn, Wr) < 1e-4
 
 
+@pytest.mark.parametrize("model,name,Hp,gamma", [("bsc", "bsc256", 12, 4), ("tsc", "tsc", 8, 3)])
+def test_factor_b_overlap_gives_the_same_mstep(model, name, Hp, gamma):
+    """B factored by the E-step on its second stream (PROSPER_FLAG_FACTOR_B)
+    and the plain M-step give the same result; a second accumulating E-step
+    discards the prepared factor."""
+    import torch
+    from paper_1908_06843_amd import api
+    Y, W, pi, sigma, wl = problem(name, 1500, "init")
+    dev = torch.device("cuda", 0)
+    Yd, Wd = torch.tensor(Y, device=dev), torch.tensor(W, device=dev)
+    outs = []
+    for fb in (False, True):
+        ctx = api.Context(0)
+        acc = api.new_acc(model, wl.D, wl.H)
+        api.estep(Yd, Wd, pi, sigma, Hprime=Hp, gamma=gamma, model=model, acc=acc, want=(),
+                  ctx=ctx, factor_b=fb)
+        Wn = torch.empty_like(Wd)
+        th = torch.empty(2, dtype=torch.float64, device=dev)
+        api.mstep(acc, Wd, model=model, W_new=Wn, theta_new=th, ctx=ctx)
+        torch.cuda.synchronize()
+        outs.append((Wn.cpu().numpy(), th.cpu().numpy()))
+    # the overlapped call leaves CUs to the factorisation, so the A sums are
+    # grouped differently: equal up to FP32 summation order
+    assert rel(outs[1][0], outs[0][0]) < 1e-5
+    np.testing.assert_allclose(outs[1][1], outs[0][1], rtol=1e-6)
+    # factor prepared, then invalidated by another accumulating call on the same acc
+    ctx = api.Context(0)
+    acc = api.new_acc(model, wl.D, wl.H)
+    api.estep(Yd[:700], Wd, pi, sigma, Hprime=Hp, gamma=gamma, model=model, acc=acc, want=(),
+              ctx=ctx, factor_b=True)
+    api.estep(Yd[700:], Wd, pi, sigma, Hprime=Hp, gamma=gamma, model=model, acc=acc, want=(),
+              ctx=ctx)
+    Wn = torch.empty_like(Wd)
+    th = torch.empty(2, dtype=torch.float64, device=dev)
+    api.mstep(acc, Wd, model=model, W_new=Wn, theta_new=th, ctx=ctx)
+    torch.cuda.synchronize()
+    assert rel(Wn.cpu().numpy(), outs[0][0]) < 1e-4
+
+
 def test_em_bars_trajectory_and_monotone_free_energy():
     """Ten exact EM iterations on bars, all on the GPU (parameters stay on the
     device), against the oracle's trajectory; the free energy rises."""
