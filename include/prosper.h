@@ -208,10 +208,14 @@ prosper_status prosper_mstep(prosper_ctx* ctx, const prosper_args* args,
 typedef struct prosper_server prosper_server;
 
 /* Start a server.  It copies W (device or host pointer, D x H FP32) once and
- * keeps it, its derived tables and the state tables resident.  Requests are
- * admitted while the device memory they need fits in mem_budget_bytes and
- * fewer than max_inflight are on the GPU; admitted requests run concurrently
- * on `n_streams` HIP streams (1..8).  queue_capacity bounds pending requests. */
+ * keeps it, its derived tables and the state tables resident.  Queued
+ * requests with the same (Hprime, gamma, topk) are batched into one launch;
+ * batches are admitted while the device memory they need fits in
+ * mem_budget_bytes and fewer than max_inflight are on the GPU, and run
+ * concurrently on `n_streams` HIP streams (1..8).  queue_capacity bounds
+ * pending requests.  The server holds mem_budget_bytes of device memory and
+ * twice that of pinned host memory (output staging, and an ingress area into
+ * which submit copies request inputs). */
 prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_device,
                              int32_t model, int32_t D, int32_t H, double pi,
                              double sigma, int32_t precision, size_t mem_budget_bytes,
@@ -219,8 +223,9 @@ prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_devi
                              int32_t queue_capacity, prosper_server** out);
 
 /* Queue one request of `npatches` points (host buffer Y_host, npatches x D).
- * The server thread reads Y_host when it admits the request, so the buffer
- * must stay valid until prosper_serve_wait returns for this id.  The per-point
+ * Y_host is copied into the ingress area during the call when it has room;
+ * otherwise the server thread reads Y_host when it launches the request, so
+ * the buffer must stay valid until prosper_serve_wait returns for this id.  The per-point
  * outputs in out_host are host buffers with the layouts of prosper_point_out
  * (NULL to skip) and are filled when the request completes.  Returns EBUSY
  * when the queue is full and EINVAL for a request larger than the budget. */

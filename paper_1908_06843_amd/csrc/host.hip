@@ -400,8 +400,8 @@ int32_t prosper_profile_read(prosper_ctx* c, int32_t cap, const char** names, do
   for (const std::string& n : c->prof_order) {
     if (i < cap) {
       // the names are string literals of this library
-      static const char* known[] = {"prep", "project_select", "states_lin", "states_max",
-                                    "stats", "mstep"};
+      static const char* known[] = {"prep",  "project_select", "states_lin", "states_max",
+                                    "stats", "mstep_factor",   "mstep"};
       const char* nm = "";
       for (const char* k : known)
         if (n == k) nm = k;

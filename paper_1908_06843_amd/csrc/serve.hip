@@ -3,17 +3,21 @@
 // data point) with continuous batching.
 //
 // One scheduler thread owns the device side.  Requests wait in a FIFO
-// queue; a request is admitted as soon as (a) fewer than max_inflight
-// requests are on the GPU and (b) its buffers fit in the device memory pool
-// (mem_budget_bytes, first-fit).  Admitted requests are launched on the
-// least-loaded of n_streams HIP streams, so requests that arrive while
-// others run overlap with them on the device.  Completion is detected with
-// HIP events; the scheduler copies the outputs from the pinned staging
-// area into the caller's buffers, returns the memory and admits the next
-// requests.  The dictionary, its derived tables (projection rows, Gram
-// matrix, norms) and the state tables are built once and stay resident.
-// No computation couples two requests, so a result is the same alone and
-// in any mix.
+// queue.  Whenever fewer than max_inflight batches are on the GPU, the
+// scheduler forms a batch from the head of the queue: the head request plus
+// the queued requests with the same (H', gamma, topk), up to a row limit,
+// whose combined buffers fit in the device memory pool (mem_budget_bytes,
+// first-fit); a request that does not fit waits for memory to be returned.
+// A batch costs one staging copy, one set of kernel launches and one copy
+// back per output, and runs on the least-loaded of n_streams HIP streams,
+// so batches formed while others run overlap with them on the device.
+// Completion is detected with HIP events; the scheduler then copies each
+// member's rows from the pinned staging area into its caller's buffers,
+// returns the memory and forms the next batches.  The dictionary, its
+// derived tables (projection rows, Gram matrix, norms) and the state tables
+// are built once and stay resident.  Every output of a point depends only on
+// that point and the dictionary, so a result is the same alone and in any
+// batch or mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -81,10 +85,21 @@ struct Req {
   Clock::time_point t_submit, t_done;
   prosper_status status = PROSPER_OK;
   bool done = false;
-  // device side
+  int64_t row0 = 0;  // first row inside its batch
+  // pinned copy of Y made by the submitting thread (ingress pool), if any
+  size_t in_off = 0, in_bytes = 0;
+  bool staged = false;
+};
+
+struct Batch {
+  std::vector<Req*> reqs;
+  int Hp = 0, gamma = 0, topk = 0;
+  int64_t n = 0;
   size_t off = 0, bytes = 0;
   int stream = -1;
   hipEvent_t ev = nullptr;
+  prosper_status status = PROSPER_OK;
+  bool w_sel = false, w_sm = false, w_logL = false, w_flag = false, w_tm = false, w_tq = false;
   // layout inside the pool piece
   size_t o_Y, o_sel, o_bc, o_yy, o_sm, o_redo, o_cnt, o_logL, o_flag, o_tm, o_tq;
 };
@@ -95,26 +110,33 @@ struct TableDev {
   int64_t count = 0;
 };
 
-size_t layout(Req& r, int D) {
+// Device bytes of n rows with H' candidates and topk states (one piece).
+size_t layout_bytes(int64_t n, int Hp, int topk, int D, Batch* b) {
   size_t o = 0;
-  auto take = [&](size_t n) {
+  auto take = [&](size_t m) {
     o = (o + 255) & ~(size_t)255;
     size_t at = o;
-    o += n;
+    o += m;
     return at;
   };
-  const size_t N = (size_t)r.n, Hp = (size_t)r.Hp, K = (size_t)r.topk;
-  r.o_Y = take(N * D * 4);
-  r.o_sel = take(N * Hp * 4);
-  r.o_bc = take(N * Hp * 4);
-  r.o_yy = take(N * 4);
-  r.o_sm = take(N * Hp * 4);
-  r.o_redo = take(N * 4);
-  r.o_cnt = take(4);
-  r.o_logL = take(N * 4);
-  r.o_flag = take(N);
-  r.o_tm = take(N * K * 4 * 2);
-  r.o_tq = take(N * K * 4);
+  const size_t N = (size_t)n, H1 = (size_t)Hp, K = (size_t)topk;
+  const size_t oY = take(N * D * 4), osel = take(N * H1 * 4), obc = take(N * H1 * 4),
+               oyy = take(N * 4), osm = take(N * H1 * 4), oredo = take(N * 4), ocnt = take(4),
+               ologL = take(N * 4), oflag = take(N), otm = take(N * K * 4 * 2),
+               otq = take(N * K * 4);
+  if (b) {
+    b->o_Y = oY;
+    b->o_sel = osel;
+    b->o_bc = obc;
+    b->o_yy = oyy;
+    b->o_sm = osm;
+    b->o_redo = oredo;
+    b->o_cnt = ocnt;
+    b->o_logL = ologL;
+    b->o_flag = oflag;
+    b->o_tm = otm;
+    b->o_tq = otq;
+  }
   return (o + 255) & ~(size_t)255;
 }
 
@@ -132,12 +154,15 @@ struct prosper_server {
   int32_t* prep_redo = nullptr;
   char* dev_pool = nullptr;
   char* pin_pool = nullptr;
+  char* in_pool = nullptr;  // pinned ingress area for request inputs
   Pool pool;
+  Pool in_free;             // shared with submit: lock held
   std::vector<hipStream_t> streams;
   std::vector<int> stream_load;
   std::map<std::pair<int, int>, TableDev> tables;
   std::deque<Req*> queue;
-  std::vector<Req*> inflight;
+  std::vector<Batch*> inflight;     // scheduler thread only
+  std::vector<hipEvent_t> ev_pool;  // scheduler thread only
   std::map<uint64_t, Req*> reqs;
   uint64_t next_id = 1;
   std::mutex mu;
@@ -169,126 +194,228 @@ prosper_status table_for(prosper_server* s, int Hp, int gamma, TableDev** out) {
   return PROSPER_OK;
 }
 
-// Launch one admitted request (scheduler thread, lock held).
-void launch(prosper_server* s, Req* r) {
+// Rows of one batch at most (unless its head request alone is larger): keeps
+// the wait of a small request behind the big ones it is batched with short.
+static constexpr int64_t BATCH_ROWS = 2048;
+
+// Form the next batch from the queue (lock held).  Returns nullptr when the
+// queue is empty or the head request does not fit in the free memory.
+Batch* form_batch(prosper_server* s) {
+  if (s->queue.empty()) return nullptr;
+  Req* head = s->queue.front();
+  Batch* b = new (std::nothrow) Batch();
+  if (!b) return nullptr;
+  b->Hp = head->Hp;
+  b->gamma = head->gamma;
+  b->topk = head->topk;
+  std::vector<size_t> pick;  // queue positions, in order
+  int64_t rows = 0;
+  const int64_t limit = std::max<int64_t>(head->n, BATCH_ROWS);
+  for (size_t i = 0; i < s->queue.size() && i < 64; ++i) {
+    Req* r = s->queue[i];
+    if (r->Hp != b->Hp || r->gamma != b->gamma || r->topk != b->topk) continue;
+    if (rows + r->n > limit) break;
+    pick.push_back(i);
+    rows += r->n;
+  }
+  // largest prefix of the picks that fits in the pool
+  size_t off = 0;
+  while (!pick.empty()) {
+    int64_t n = 0;
+    for (size_t i : pick) n += s->queue[i]->n;
+    const size_t bytes = layout_bytes(n, b->Hp, b->topk, s->D, b);
+    if (s->pool.alloc(bytes, &off)) {
+      b->n = n;
+      b->bytes = bytes;
+      b->off = off;
+      break;
+    }
+    pick.pop_back();
+  }
+  if (pick.empty()) {
+    delete b;
+    return nullptr;
+  }
+  int64_t row = 0;
+  for (size_t i : pick) {
+    Req* r = s->queue[i];
+    r->row0 = row;
+    row += r->n;
+    b->reqs.push_back(r);
+    b->w_sel |= r->out.sel != nullptr;
+    b->w_sm |= r->out.s_mean != nullptr;
+    b->w_logL |= r->out.logL != nullptr;
+    b->w_flag |= r->out.flagged != nullptr;
+    b->w_tm |= r->out.top_mask != nullptr && r->topk > 0;
+    b->w_tq |= r->out.top_q != nullptr && r->topk > 0;
+  }
+  for (size_t k = pick.size(); k-- > 0;) s->queue.erase(s->queue.begin() + pick[k]);
+  return b;
+}
+
+// Launch one batch (scheduler thread; the batch's pool piece is its own, so
+// no lock is needed).
+void launch(prosper_server* s, Batch* b) {
   TableDev* tab = nullptr;
-  prosper_status st = table_for(s, r->Hp, r->gamma, &tab);
+  prosper_status st = table_for(s, b->Hp, b->gamma, &tab);
   if (st != PROSPER_OK) {
-    r->status = st;
+    b->status = st;
     return;
   }
   int best = 0;
   for (int i = 1; i < s->n_streams; ++i)
     if (s->stream_load[i] < s->stream_load[best]) best = i;
-  r->stream = best;
+  b->stream = best;
   s->stream_load[best]++;
   hipStream_t stm = s->streams[best];
-  char* dev = s->dev_pool + r->off;
-  char* pin = s->pin_pool + r->off;
-  std::memcpy(pin + r->o_Y, r->Y, (size_t)r->n * s->D * 4);
-  hipError_t e = hipMemcpyAsync(dev + r->o_Y, pin + r->o_Y, (size_t)r->n * s->D * 4,
-                                hipMemcpyHostToDevice, stm);
+  char* dev = s->dev_pool + b->off;
+  char* pin = s->pin_pool + b->off;
+  const size_t row_bytes = (size_t)s->D * 4;
+  hipError_t e = hipSuccess;
+  bool all_staged = true;
+  for (Req* r : b->reqs) all_staged &= r->staged;
+  if (all_staged) {
+    // inputs were copied to pinned memory by the submitting threads
+    for (Req* r : b->reqs)
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dev + b->o_Y + (size_t)r->row0 * row_bytes, s->in_pool + r->in_off,
+                           (size_t)r->n * row_bytes, hipMemcpyHostToDevice, stm);
+  } else {
+    for (Req* r : b->reqs) {
+      const char* src = r->staged ? s->in_pool + r->in_off : reinterpret_cast<const char*>(r->Y);
+      std::memcpy(pin + b->o_Y + (size_t)r->row0 * row_bytes, src, (size_t)r->n * row_bytes);
+    }
+    e = hipMemcpyAsync(dev + b->o_Y, pin + b->o_Y, (size_t)b->n * row_bytes,
+                       hipMemcpyHostToDevice, stm);
+  }
   Scratch sc;
-  sc.sel = reinterpret_cast<int32_t*>(dev + r->o_sel);
-  sc.bc = reinterpret_cast<float*>(dev + r->o_bc);
-  sc.yy = reinterpret_cast<float*>(dev + r->o_yy);
-  sc.s_mean = reinterpret_cast<float*>(dev + r->o_sm);
-  sc.redo_list = reinterpret_cast<int32_t*>(dev + r->o_redo);
-  sc.redo_count = reinterpret_cast<int32_t*>(dev + r->o_cnt);
+  sc.sel = reinterpret_cast<int32_t*>(dev + b->o_sel);
+  sc.bc = reinterpret_cast<float*>(dev + b->o_bc);
+  sc.yy = reinterpret_cast<float*>(dev + b->o_yy);
+  sc.s_mean = reinterpret_cast<float*>(dev + b->o_sm);
+  sc.redo_list = reinterpret_cast<int32_t*>(dev + b->o_redo);
+  sc.redo_count = reinterpret_cast<int32_t*>(dev + b->o_cnt);
   sc.ss = nullptr;
   sc.partA = sc.partB = nullptr;
-  float* logL = reinterpret_cast<float*>(dev + r->o_logL);
-  uint8_t* flag = reinterpret_cast<uint8_t*>(dev + r->o_flag);
-  uint32_t* tm = r->topk ? reinterpret_cast<uint32_t*>(dev + r->o_tm) : nullptr;
-  float* tq = r->topk ? reinterpret_cast<float*>(dev + r->o_tq) : nullptr;
+  float* logL = reinterpret_cast<float*>(dev + b->o_logL);
+  uint8_t* flag = reinterpret_cast<uint8_t*>(dev + b->o_flag);
+  uint32_t* tm = b->topk ? reinterpret_cast<uint32_t*>(dev + b->o_tm) : nullptr;
+  float* tq = b->topk ? reinterpret_cast<float*>(dev + b->o_tq) : nullptr;
   if (e == hipSuccess) e = hipMemsetAsync(sc.redo_count, 0, 4, stm);
   if (e == hipSuccess)
-    e = launch_estep_core(s->model, s->prec, reinterpret_cast<const float*>(dev + r->o_Y), r->n,
-                          s->D, s->H, r->Hp, r->gamma, tab->count, tab->act, tab->sgn, s->prep,
-                          sc, flag, logL, tm, tq, r->topk, nullptr, nullptr, nullptr, s->num_cu,
+    e = launch_estep_core(s->model, s->prec, reinterpret_cast<const float*>(dev + b->o_Y), b->n,
+                          s->D, s->H, b->Hp, b->gamma, tab->count, tab->act, tab->sgn, s->prep,
+                          sc, flag, logL, tm, tq, b->topk, nullptr, nullptr, nullptr, s->num_cu,
                           stm);
   // outputs back to the pinned area
   auto d2h = [&](size_t o, size_t n) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(pin + o, dev + o, n, hipMemcpyDeviceToHost, stm);
   };
-  const size_t N = (size_t)r->n, Hp = (size_t)r->Hp, K = (size_t)r->topk;
+  const size_t N = (size_t)b->n, Hp = (size_t)b->Hp, K = (size_t)b->topk;
   const size_t tmw = (s->model == PROSPER_TSC) ? 2 : 1;
-  if (r->out.sel) d2h(r->o_sel, N * Hp * 4);
-  if (r->out.s_mean) d2h(r->o_sm, N * Hp * 4);
-  if (r->out.logL) d2h(r->o_logL, N * 4);
-  if (r->out.flagged) d2h(r->o_flag, N);
-  if (r->out.top_mask && K) d2h(r->o_tm, N * K * 4 * tmw);
-  if (r->out.top_q && K) d2h(r->o_tq, N * K * 4);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(r->ev, stm);
+  if (b->w_sel) d2h(b->o_sel, N * Hp * 4);
+  if (b->w_sm) d2h(b->o_sm, N * Hp * 4);
+  if (b->w_logL) d2h(b->o_logL, N * 4);
+  if (b->w_flag) d2h(b->o_flag, N);
+  if (b->w_tm) d2h(b->o_tm, N * K * 4 * tmw);
+  if (b->w_tq) d2h(b->o_tq, N * K * 4);
+  if (e == hipSuccess) {
+    if (!s->ev_pool.empty()) {
+      b->ev = s->ev_pool.back();
+      s->ev_pool.pop_back();
+    } else {
+      e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->ev, stm);
   if (e != hipSuccess) {
     s->err = std::string("serve launch: ") + hipGetErrorString(e);
-    r->status = PROSPER_EDEVICE;
+    b->status = PROSPER_EDEVICE;
   }
 }
 
-void finish(prosper_server* s, Req* r) {
-  const char* pin = s->pin_pool + r->off;
-  const size_t N = (size_t)r->n, Hp = (size_t)r->Hp, K = (size_t)r->topk;
+// Copy each member's rows of a completed batch to its caller's buffers and
+// return the batch's stream slot, event and memory (scheduler thread, no lock).
+void deliver(prosper_server* s, Batch* b) {
+  const char* pin = s->pin_pool + b->off;
+  const size_t Hp = (size_t)b->Hp, K = (size_t)b->topk;
   const size_t tmw = (s->model == PROSPER_TSC) ? 2 : 1;
-  if (r->status == PROSPER_OK) {
-    if (r->out.sel) std::memcpy(r->out.sel, pin + r->o_sel, N * Hp * 4);
-    if (r->out.s_mean) std::memcpy(r->out.s_mean, pin + r->o_sm, N * Hp * 4);
-    if (r->out.logL) std::memcpy(r->out.logL, pin + r->o_logL, N * 4);
-    if (r->out.flagged) std::memcpy(r->out.flagged, pin + r->o_flag, N);
-    if (r->out.top_mask && K) std::memcpy(r->out.top_mask, pin + r->o_tm, N * K * 4 * tmw);
-    if (r->out.top_q && K) std::memcpy(r->out.top_q, pin + r->o_tq, N * K * 4);
+  for (Req* r : b->reqs) {
+    r->status = b->status;
+    if (b->status != PROSPER_OK) continue;
+    const size_t n = (size_t)r->n, r0 = (size_t)r->row0;
+    if (r->out.sel) std::memcpy(r->out.sel, pin + b->o_sel + r0 * Hp * 4, n * Hp * 4);
+    if (r->out.s_mean) std::memcpy(r->out.s_mean, pin + b->o_sm + r0 * Hp * 4, n * Hp * 4);
+    if (r->out.logL) std::memcpy(r->out.logL, pin + b->o_logL + r0 * 4, n * 4);
+    if (r->out.flagged) std::memcpy(r->out.flagged, pin + b->o_flag + r0, n);
+    if (r->out.top_mask && K)
+      std::memcpy(r->out.top_mask, pin + b->o_tm + r0 * K * 4 * tmw, n * K * 4 * tmw);
+    if (r->out.top_q && K) std::memcpy(r->out.top_q, pin + b->o_tq + r0 * K * 4, n * K * 4);
   }
-  if (r->ev) hipEventDestroy(r->ev);
-  r->ev = nullptr;
-  if (r->stream >= 0) s->stream_load[r->stream]--;
-  s->pool.release(r->off, r->bytes);
-  r->t_done = Clock::now();
-  r->done = true;
+  if (b->ev) s->ev_pool.push_back(b->ev);
+  b->ev = nullptr;
+  if (b->stream >= 0) s->stream_load[b->stream]--;
+  s->pool.release(b->off, b->bytes);
 }
 
+// The scheduler.  Only the queue, the request table and the done flags are
+// shared with submit/wait and need the lock (forming a batch takes its memory
+// under the lock too); staging copies, launches, completion queries and
+// output copies run without it, so callers are never blocked behind them.
+// While batches are on the GPU it polls their events without sleeping (a
+// sleep would add the timer slack to every latency).
 void scheduler(prosper_server* s) {
   hipSetDevice(s->device);
-  std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<Batch*> admit, done;
   while (true) {
-    // admit in arrival order while slots and memory allow
-    while (!s->queue.empty() && (int)s->inflight.size() < s->max_inflight) {
-      Req* r = s->queue.front();
-      size_t off = 0;
-      if (!s->pool.alloc(r->bytes, &off)) break;
-      s->queue.pop_front();
-      r->off = off;
-      launch(s, r);
-      if (r->status != PROSPER_OK) {
-        finish(s, r);
-        s->cv_done.notify_all();
-        continue;
+    admit.clear();
+    done.clear();
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->inflight.empty() && s->queue.empty()) {
+        if (s->stopping) break;
+        s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
+        if (s->stopping && s->queue.empty()) break;
       }
-      s->inflight.push_back(r);
+      while ((int)(s->inflight.size() + admit.size()) < s->max_inflight) {
+        Batch* b = form_batch(s);
+        if (!b) break;
+        admit.push_back(b);
+      }
     }
-    // retire completed requests
-    bool any = false;
+    for (Batch* b : admit) {
+      launch(s, b);
+      if (b->status != PROSPER_OK) done.push_back(b);
+      else s->inflight.push_back(b);
+    }
     for (size_t i = 0; i < s->inflight.size();) {
-      Req* r = s->inflight[i];
-      hipError_t q = hipEventQuery(r->ev);
+      Batch* b = s->inflight[i];
+      const hipError_t q = hipEventQuery(b->ev);
       if (q == hipErrorNotReady) {
         ++i;
         continue;
       }
-      if (q != hipSuccess) r->status = PROSPER_EDEVICE;
-      finish(s, r);
+      if (q != hipSuccess) b->status = PROSPER_EDEVICE;
+      done.push_back(b);
       s->inflight.erase(s->inflight.begin() + i);
-      any = true;
     }
-    if (any) s->cv_done.notify_all();
-    if (s->stopping && s->queue.empty() && s->inflight.empty()) break;
-    if (s->inflight.empty() && s->queue.empty()) {
-      s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
-    } else if (!any) {
-      // requests on the GPU: poll their events again shortly
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-      lk.lock();
+    for (Batch* b : done) deliver(s, b);
+    if (!done.empty()) {
+      const Clock::time_point now = Clock::now();
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (Batch* b : done)
+          for (Req* r : b->reqs) {
+            if (r->staged) s->in_free.release(r->in_off, r->in_bytes);
+            r->staged = false;
+            r->t_done = now;
+            r->done = true;
+          }
+      }
+      s->cv_done.notify_all();
+      for (Batch* b : done) delete b;
+    } else if (admit.empty()) {
+      std::this_thread::yield();
     }
   }
 }
@@ -337,6 +464,7 @@ prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_devi
   if (e == hipSuccess) e = hipMalloc(&s->prep_redo, 4);
   if (e == hipSuccess) e = hipMalloc(&s->dev_pool, mem_budget_bytes);
   if (e == hipSuccess) e = hipHostMalloc(&s->pin_pool, mem_budget_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&s->in_pool, mem_budget_bytes, hipHostMallocDefault);
   for (int i = 0; e == hipSuccess && i < n_streams; ++i) {
     hipStream_t st;
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -353,6 +481,7 @@ prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_devi
     return PROSPER_EDEVICE;
   }
   s->pool.init(mem_budget_bytes);
+  s->in_free.init(mem_budget_bytes);
   s->stream_load.assign(n_streams, 0);
   s->th = std::thread(scheduler, s);
   *out = s;
@@ -383,18 +512,32 @@ prosper_status prosper_serve_submit(prosper_server* s, const float* Y_host, int6
   r->gamma = gamma;
   r->topk = topk;
   if (out_host) r->out = *out_host;
-  r->bytes = layout(*r, s->D);
-  if (r->bytes > s->budget) {
+  if (layout_bytes(npatches, Hprime, topk, s->D, nullptr) > s->budget) {
     delete r;
     return PROSPER_EINVAL;
   }
+  const Clock::time_point t_submit = Clock::now();
+  // copy the input to the pinned ingress area on this thread when it has
+  // room (otherwise the scheduler stages it when the request is launched)
+  const size_t in_bytes = (size_t)npatches * s->D * 4;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if ((int)s->queue.size() >= s->qcap || s->stopping) {
+      delete r;
+      return PROSPER_EBUSY;
+    }
+    r->staged = s->in_free.alloc(in_bytes, &r->in_off);
+    if (r->staged) r->in_bytes = in_bytes;
+  }
+  if (r->staged) std::memcpy(s->in_pool + r->in_off, Y_host, in_bytes);
   std::lock_guard<std::mutex> g(s->mu);
-  if ((int)s->queue.size() >= s->qcap || s->stopping) {
+  if (s->stopping) {
+    if (r->staged) s->in_free.release(r->in_off, r->in_bytes);
     delete r;
     return PROSPER_EBUSY;
   }
   r->id = s->next_id++;
-  r->t_submit = Clock::now();
+  r->t_submit = t_submit;
   s->reqs[r->id] = r;
   s->queue.push_back(r);
   *req_id = r->id;
@@ -437,11 +580,13 @@ prosper_status prosper_serve_stop(prosper_server* s) {
     hipFree(kv.second.sgn);
   }
   for (hipStream_t st : s->streams) hipStreamDestroy(st);
+  for (hipEvent_t ev : s->ev_pool) hipEventDestroy(ev);
   if (s->W) hipFree(s->W);
   if (s->prep_mem) hipFree(s->prep_mem);
   if (s->prep_redo) hipFree(s->prep_redo);
   if (s->dev_pool) hipFree(s->dev_pool);
   if (s->pin_pool) hipHostFree(s->pin_pool);
+  if (s->in_pool) hipHostFree(s->in_pool);
   delete s;
   return PROSPER_OK;
 }
