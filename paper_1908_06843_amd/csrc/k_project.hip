@@ -441,11 +441,19 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
   __syncthreads();
 
   // ---- 2. b = P y for the tile: MFMA, FP32 accumulation
-  f32x4 acc[4][4];
+  // BF16: head*head products in acc, the two cross products in accx (kept
+  // apart so that the accumulation error of each is relative to its own
+  // magnitude); FP32 uses acc only
+  constexpr int NX = (PREC == PROSPER_BF16) ? 4 : 1;
+  f32x4 acc[4][4], accx[NX][4];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[s][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < NX; ++s)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) accx[s][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
 #pragma unroll
   for (int gi = 0; gi < GPW; ++gi) {
@@ -548,9 +556,10 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
               f32x4& c = acc[gi * MT + mt][nt];
+              f32x4& cx = accx[(gi * MT + mt) % NX][nt];
               c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bhv, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], blv, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bhv, c, 0, 0, 0);
+              cx = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], blv, cx, 0, 0, 0);
+              cx = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bhv, cx, 0, 0, 0);
             }
           }
         }
@@ -578,7 +587,9 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          Bs[(mt * 16 + 4 * q + i) * Hs + g * 64 + nt * 16 + r16] = acc[gi * MT + mt][nt][i];
+          Bs[(mt * 16 + 4 * q + i) * Hs + g * 64 + nt * 16 + r16] =
+              (PREC == PROSPER_BF16) ? acc[gi * MT + mt][nt][i] + accx[(gi * MT + mt) % NX][nt][i]
+                                     : acc[gi * MT + mt][nt][i];
   }
   __syncthreads();
 
@@ -753,13 +764,16 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
   // Bound on |computed b - exact b| per unit of ||y|| ||P_h|| (Cauchy-Schwarz
   // on sum |y_d P_hd|).  FP32: every product rounded once, at most D + 1
   // roundings along the FP32 accumulation (padding adds exact zeros).  BF16
-  // head/tail split: head*head, head*tail and tail*head are exact in FP32;
-  // the dropped tail*tail and the two split remainders are each at most
-  // 2^-16 |y_d P_hd|, and 3 D + 1 accumulations follow.  1% slack on both.
+  // head/tail split: the dropped tail*tail and the two split remainders are
+  // each at most 2^-16 |y_d P_hd|; head*head, head*tail and tail*head are
+  // exact in FP32; the head*head sum sees D + 1 roundings, the cross sum
+  // (terms below 2^-7 of the head*head ones) 2 D + 1, and one rounding adds
+  // the two.  3% slack.
   const double u = 1.0 / 16777216.0;  // 2^-24
-  const float kappa = (prec == PROSPER_FP32)
-                          ? (float)(1.01 * (D + 2) * u)
-                          : (float)(1.01 * (3.0 / 65536.0 + (3.0 * D + 2) * u));
+  const float kappa =
+      (prec == PROSPER_FP32)
+          ? (float)(1.01 * (D + 2) * u)
+          : (float)(1.03 * (3.0 / 65536.0 + (D + 2) * u + (2.0 * D + 1) * u / 128.0 + u));
   const int tm = choose_tm(Dp, H, prec);
   const size_t lds = project_lds_bytes(Dp, H, prec, tm);
   const int Hpad = round_up(H, 64);
