@@ -132,15 +132,17 @@ static constexpr int AT_PTS = 64;         // points per tile (two k-steps of 32)
 static constexpr int AT_LD = AT_PTS + 8;  // bf16 row stride of the transposed S tile
 static constexpr int AT_YS = 258;         // float row stride of the Y tile
 
-template <int SELN>  // (sel, <s>) entries per thread and tile: 64 H' <= 256 SELN
+// FULL: D = H = 256, every row and column tile present (no per-MFMA tests).
+template <int SELN, bool FULL>  // (sel, <s>) entries per thread and tile: 64 H' <= 256 SELN
 __global__ __launch_bounds__(256, 1) void k_stats_A_mfma(
     const float* __restrict__ Y, int64_t N, int D, int H, int Hp, const int32_t* __restrict__ sel,
     const float* __restrict__ s_mean, float* __restrict__ partA) {
   __shared__ __align__(16) float Yf[AT_PTS * AT_YS];
   __shared__ __align__(16) bf16 Sh[256 * AT_LD], Sl[256 * AT_LD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int Dt = (D + 15) / 16, Ht = (H + 15) / 16;
+  const int Dt = FULL ? 16 : (D + 15) / 16, Ht = FULL ? 16 : (H + 15) / 16;
   const int64_t ntiles = (N + AT_PTS - 1) / AT_PTS;
   for (int e = tid; e < 256 * AT_LD; e += 256) {
     Sh[e] = (bf16)0.0f;
@@ -217,31 +219,42 @@ __global__ __launch_bounds__(256, 1) void k_stats_A_mfma(
     if (t + gridDim.x < ntiles) fetch(t + gridDim.x);
 #pragma unroll
     for (int ks = 0; ks < AT_PTS / 32; ++ks) {
+      // A fragments of the wave's four row tiles once per k-step (the
+      // transpose happens here), then each B fragment is read once and
+      // used by all four
+      bf16x8 ah[4], al[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int rt = wave + 4 * a;
-        if (rt < Dt) {
-          bf16x8 ah, al;
-          const float* col = &Yf[(32 * ks + 8 * q) * AT_YS + 16 * rt + r16];
+        const float* col = &Yf[(32 * ks + 8 * q) * AT_YS + 16 * (rt < Dt ? rt : 0) + r16];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float v = col[e * AT_YS];
-            const bf16 hv = (bf16)v;
-            ah[e] = hv;
-            al[e] = (bf16)(v - (float)hv);
-          }
+        for (int e = 0; e < 8; ++e) {
+          const float v = col[e * AT_YS];
+          const bf16 hv = (bf16)v;
+          ah[a][e] = hv;
+          al[a][e] = (bf16)(v - (float)hv);
+        }
+      }
 #pragma unroll
-          for (int ct = 0; ct < 16; ++ct) {
-            if (ct < Ht) {
-              const int ob = (16 * ct + r16) * AT_LD + 32 * ks + 8 * q;
-              const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Sh[ob]);
-              const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Sl[ob]);
-              f32x4& c = acc[a][ct];
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-            }
-          }
+      for (int ct = 0; ct < 16; ++ct) {
+        if (FULL || ct < Ht) {
+          const int ob = (16 * ct + r16) * AT_LD + 32 * ks + 8 * q;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Sh[ob]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Sl[ob]);
+          // three passes over the four row tiles: consecutive MFMAs write
+          // different accumulators, so none waits for the previous result
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (FULL || wave + 4 * a < Dt)
+              acc[a][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh, acc[a][ct], 0, 0, 0);
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (FULL || wave + 4 * a < Dt)
+              acc[a][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl, acc[a][ct], 0, 0, 0);
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (FULL || wave + 4 * a < Dt)
+              acc[a][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh, acc[a][ct], 0, 0, 0);
         }
       }
     }
@@ -473,12 +486,16 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
     int cap = pl.mfma_wgs - reserve_cu;
     if (cap < 1) cap = 1;
     const int nwg = (int)(ntiles < cap ? ntiles : cap);
-    if (Hp <= 16)
-      hipLaunchKernelGGL(k_stats_A_mfma<4>, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, H, Hp,
-                         s.sel, s.s_mean, s.partA);
+    const bool full = D == 256 && H == 256;
+    if (Hp <= 16 && full)
+      hipLaunchKernelGGL((k_stats_A_mfma<4, true>), dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D,
+                         H, Hp, s.sel, s.s_mean, s.partA);
+    else if (Hp <= 16)
+      hipLaunchKernelGGL((k_stats_A_mfma<4, false>), dim3((unsigned)nwg), dim3(256), 0, st, Y, N,
+                         D, H, Hp, s.sel, s.s_mean, s.partA);
     else
-      hipLaunchKernelGGL(k_stats_A_mfma<8>, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, H, Hp,
-                         s.sel, s.s_mean, s.partA);
+      hipLaunchKernelGGL((k_stats_A_mfma<8, false>), dim3((unsigned)nwg), dim3(256), 0, st, Y, N,
+                         D, H, Hp, s.sel, s.s_mean, s.partA);
     const int64_t n = (int64_t)D * H;
     hipLaunchKernelGGL(k_stats_A_reduce, dim3((unsigned)((n / 4 + 256) / 256)), dim3(256), 0, st,
                        D, H, nwg, s.partA, A);
