@@ -296,6 +296,10 @@ __global__ __launch_bounds__(64) void k_states_tree(
         for (int j = i + 1; j < HP; ++j) ss_out[(int64_t)(q++) * N + n] = R.P[i][j] * R.invZ;
       }
     }
+  } else if (live && ss_out) {
+    // handed to the exact kernel, which adds this point's block to B itself
+#pragma unroll
+    for (int q = 0; q < HP * (HP + 1) / 2; ++q) ss_out[(int64_t)q * N + n] = 0.0f;
   }
   if (scal) {
     double a0 = R.ok ? (double)R.kmean : 0.0, a1 = R.ok ? R.lL : 0.0;
