@@ -1,6 +1,7 @@
 // Host side of libprosper: the C ABI of prosper.h -- argument validation,
 // the canonical state table, the context (device workspace, cached state
 // tables) and the launch sequence of one E-step / M-step.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -529,7 +530,12 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   add((size_t)N * 4);
   add(need_sm ? (size_t)N * Hp * 4 : 0);
   add((size_t)N * 4);
-  add(4);
+  add(8);
+  // deferral list of the projection's exact selections (lane-per-point
+  // selection only); points beyond it are selected inside the projection
+  const int Hpad = (H + 63) / 64 * 64;
+  const int defer_cap = project_defer_capacity(N, H, Hp);
+  add((size_t)defer_cap * (Hpad + 8) * 4);
   const bool lin_acc = a->accumulate && model != PROSPER_MCA;
   const size_t npairs = (size_t)Hp * (Hp + 1) / 2;
   StatsPlan plan = stats_plan(N, D, H, c->num_cu);
@@ -549,7 +555,10 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   sc.yy = cv.take<float>((size_t)N);
   float* sm_ws = cv.take<float>(need_sm ? (size_t)N * Hp : 0);
   sc.redo_list = cv.take<int32_t>((size_t)N);
-  sc.redo_count = cv.take<int32_t>(1);
+  sc.redo_count = cv.take<int32_t>(2);
+  sc.defer_count = sc.redo_count + 1;
+  sc.defer = cv.take<float>((size_t)defer_cap * (Hpad + 8));
+  sc.defer_cap = defer_cap;
   sc.ss = cv.take<float>(lin_acc && !tree_acc ? npairs * N : 0);
   if (!(lin_acc && !tree_acc)) sc.ss = nullptr;
   sc.partA = cv.take<float>(lin_acc ? plan.partA_floats : 0);
@@ -566,7 +575,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   const int Dp2 = Dp;
   e = timed(c, "prep", s, [&] {
     hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
-                                      sc.redo_count, s);
+                                      sc.redo_count, s, sc.defer_count);
     return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp2, p, s) : e2;
   });
   float* Aacc = a->accumulate ? acc->A : nullptr;

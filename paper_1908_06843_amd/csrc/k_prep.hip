@@ -11,11 +11,13 @@
 namespace prosper {
 
 // pi, sigma from the host values or from device memory (written by the
-// M-step); also clears the running max of the projection-row norms and the
-// redo-list counter of the unrolled state walk.
+// M-step); also clears the running max of the projection-row norms, the
+// redo-list counter of the unrolled state walk and the counter of points the
+// projection hands to the deferred exact selection.
 __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
                         const double* __restrict__ theta_dev, Theta* __restrict__ th,
-                        float* __restrict__ pnorm, int32_t* __restrict__ redo_count) {
+                        float* __restrict__ pnorm, int32_t* __restrict__ redo_count,
+                        int32_t* __restrict__ defer_count) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double pi = theta_dev ? theta_dev[0] : pi_h;
   double sigma = theta_dev ? theta_dev[1] : sigma_h;
@@ -33,6 +35,7 @@ __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
   *th = t;
   *pnorm = 0.0f;
   if (redo_count) *redo_count = 0;
+  if (defer_count) *defer_count = 0;
 }
 
 // Pt32[h][d] = P[d][h] (zero for d >= D), P = W or max(W, 0) (MCA, H > 1);
@@ -131,9 +134,9 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
 // before k_norms on the same stream.
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
-                             hipStream_t st) {
+                             hipStream_t st, int32_t* defer_count) {
   hipLaunchKernelGGL(k_theta, dim3(1), dim3(64), 0, st, model, D, H, pi, sigma, theta_dev,
-                     p.theta, p.pnorm, redo_count);
+                     p.theta, p.pnorm, redo_count, defer_count);
   return hipGetLastError();
 }
 

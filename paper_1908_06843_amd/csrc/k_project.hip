@@ -25,6 +25,8 @@
 // (spread over the block's MFMAs), so the four groups of a row read one
 // whole cache line of P per block; A and B use the same map, so the
 // contraction is unchanged.
+#include <algorithm>
+
 #include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
@@ -317,6 +319,7 @@ struct SelLds {
   uint8_t fast[TM];
   uint8_t slow[TM];
   int nslow;
+  int dbase;
 };
 
 // One workgroup (4 waves) per tile of TM points:
@@ -328,8 +331,10 @@ struct SelLds {
 //      A point whose H'-th and (H'+1)-th scores are further apart than the
 //      error bound 2 delta (and the flag distance) is decided by threshold:
 //      its selection is every latent scoring at least the H'-th value.  The
-//      remaining points go through the exact per-wave path above.
-//      Without FAST every point takes the exact path.
+//      remaining points go through the exact per-wave path above: in
+//      k_select_deferred when the caller gives a deferral list with room
+//      (the b row and the thresholds are written out), else here.
+//      Without FAST every point takes the exact path here.
 template <int PREC, int TM, int RM, bool FAST>
 __global__ __launch_bounds__(256, 2) void k_project_select(
     const float* __restrict__ Y, int64_t N, int D, int Dp, int H,
@@ -337,7 +342,8 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
     const bf16* __restrict__ Pt_lo, const float* __restrict__ hn_hi,
     const float* __restrict__ hn_lo, const float* __restrict__ pnorm, int Hp, int score_abs,
     float kappa, int32_t* __restrict__ sel, float* __restrict__ bc, float* __restrict__ yy_out,
-    uint8_t* __restrict__ flagged, double* __restrict__ scal, int tile_bytes) {
+    uint8_t* __restrict__ flagged, double* __restrict__ scal, int tile_bytes,
+    float* __restrict__ defer, int defer_cap, int32_t* __restrict__ defer_count) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float yyS[TM];
   __shared__ double yydS[TM];
@@ -680,9 +686,34 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
         if (flagged) flagged[n] = 0;
       }
     }
-    // ---- 4e. the exact path for the rest
+    // ---- 4e. the exact path for the rest: the first nd of them (those that
+    // find a free slot in the deferral list) are written out for
+    // k_select_deferred, the others are selected here
     const int ns = sl.nslow;
-    for (int i = wave; i < ns; i += 4) {
+    int nd = 0;
+    if (defer_cap > 0 && ns > 0) {
+      if (threadIdx.x == 0) sl.dbase = atomicAdd(defer_count, ns);
+      __syncthreads();
+      const int dbase = sl.dbase;
+      nd = dbase < defer_cap ? min(ns, defer_cap - dbase) : 0;
+      const int Hrow = Hpad + 8;
+      for (int i = wave; i < nd; i += 4) {
+        const int r = sl.slow[i];
+        const int64_t n = n0 + r;
+        float* ent = defer + (int64_t)(dbase + i) * Hrow;
+        const float ynorm = sqrtf(yyS[r]);
+        const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+        for (int h = lane; h < Hpad; h += 64) ent[8 + h] = Bs[r * Hs + h];
+        if (lane == 0) {
+          *reinterpret_cast<int64_t*>(ent) = n;
+          ent[2] = sl.thr[r];
+          ent[3] = sl.thrN[r];
+          ent[4] = delta;
+          yy_out[n] = yyS[r];
+        }
+      }
+    }
+    for (int i = nd + wave; i < ns; i += 4) {
       const int r = sl.slow[i];
       const int64_t n = n0 + r;
       const float ynorm = sqrtf(yyS[r]);
@@ -713,6 +744,31 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
   }
 }
 
+// The exact selection of the points the projection kernel deferred, one wave
+// per point over a grid-stride loop (no LDS, so many waves per SIMD hide the
+// latency of the band re-scoring).  Entry i < min(count, cap) holds the
+// point index, its H'-th and (H'+1)-th computed scores, delta and its b row.
+template <int RM>
+__global__ __launch_bounds__(256) void k_select_deferred(
+    const float* __restrict__ defer, int defer_cap, const int32_t* __restrict__ defer_count,
+    const float* __restrict__ Y, int D, int Dp, int H, int Hp, const float* __restrict__ Pt32,
+    const float* __restrict__ hn_hi, const float* __restrict__ hn_lo, int score_abs,
+    int32_t* __restrict__ sel, float* __restrict__ bc, uint8_t* __restrict__ flagged) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cnt = min(*defer_count, defer_cap);
+  const int Hpad = round_up(H, 64);
+  const int R = Hpad / 64;
+  const int Hrow = Hpad + 8;
+  for (int i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
+    const float* ent = defer + (int64_t)i * Hrow;
+    const int64_t n = *reinterpret_cast<const int64_t*>(ent);
+    exact_select_point<RM>(ent + 8, lane, R, H, Hp, score_abs, true, ent[2], ent[3], ent[4],
+                           Y + n * D, D, Dp, Pt32, hn_hi, hn_lo, sel + n * Hp, bc + n * Hp,
+                           flagged ? flagged + n : nullptr);
+  }
+}
+
 template <int PREC, int TM, int RM, bool FAST>
 static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int Hp,
                             int score_abs, float kappa, const Prepared& p, const Scratch& s,
@@ -729,7 +785,16 @@ static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int
   const int tile_bytes = (int)(lds - (size_t)round_up(H, 64) * 8);
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(256), lds, st, Y, N, D, Dp, H, p.Pt32,
                      p.Pt_hi, p.Pt_lo, p.hn_hi, p.hn_lo, p.pnorm, Hp, score_abs, kappa, s.sel,
-                     s.bc, s.yy, flagged, scal, tile_bytes);
+                     s.bc, s.yy, flagged, scal, tile_bytes, s.defer, FAST ? s.defer_cap : 0,
+                     s.defer_count);
+  if (FAST && s.defer_cap > 0) {
+    // at most one wave per entry; 1024 workgroups are what stays resident at
+    // this kernel's register count (4 waves per SIMD)
+    const int nwg = (int)std::min<int64_t>(1024, ((int64_t)s.defer_cap + 3) / 4);
+    hipLaunchKernelGGL(k_select_deferred<RM>, dim3((unsigned)nwg), dim3(256), 0, st, s.defer,
+                       s.defer_cap, s.defer_count, Y, D, Dp, H, Hp, p.Pt32, p.hn_hi, p.hn_lo,
+                       score_abs, s.sel, s.bc, flagged);
+  }
   return hipGetLastError();
 }
 
@@ -754,6 +819,11 @@ static int choose_tm(int Dp, int H, int prec) {
   while (tm > 16 && project_lds_bytes(Dp, H, prec, tm) + static_lds_bytes(tm) > 80 * 1024)
     tm /= 2;
   return tm;
+}
+
+int project_defer_capacity(int64_t N, int H, int Hp) {
+  if (!(Hp <= FAST_HP && Hp < H) || N <= 0) return 0;
+  return (int)std::min<int64_t>(std::min<int64_t>(N, N / 4 + 1024), 1 << 24);
 }
 
 hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N, int D, int Dp,

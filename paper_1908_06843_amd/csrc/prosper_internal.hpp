@@ -65,6 +65,13 @@ struct Scratch {
   float* ss;        // H'(H'+1)/2 x N  <s_i s_j> per point, pair-major (statistics only)
   int32_t* redo_list;   // N   points the unrolled walk hands to the exact kernel
   int32_t* redo_count;  // 1   (cleared by the parameter kernel of each call)
+  // Points whose selection needs the exact path, handed by the projection
+  // kernel to a second kernel: defer_cap entries of (Hpad + 8) floats each
+  // (header: point index as int64, cH, cN, delta; then the raw b row).
+  // defer_cap == 0 keeps every such point inside the projection workgroup.
+  float* defer = nullptr;
+  int defer_cap = 0;
+  int32_t* defer_count = nullptr;  // 1 (cleared by the parameter kernel of each call)
   float* partA;         // statistics: per-group partials of A and B
   float* partB;
   StatsPlan plan;
@@ -100,9 +107,12 @@ Prepared carve_prep(void* base, int Dp, int H, int prec);
 // Launchers (each returns the first HIP error it sees).
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
-                             hipStream_t st);
+                             hipStream_t st, int32_t* defer_count = nullptr);
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
                        const Prepared& p, hipStream_t st);
+// Entries of the projection's deferral list for N points: enough for a
+// quarter of them (0 where every point takes the exact path anyway).
+int project_defer_capacity(int64_t N, int H, int Hp);
 hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N, int D, int Dp,
                                  int H, int Hp, const Prepared& p, const Scratch& s,
                                  uint8_t* flagged, double* scal, hipStream_t st);
