@@ -620,7 +620,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   if (e == hipSuccess && Aacc && model != PROSPER_MCA)
     e = timed(c, "stats", s, [&] {
       return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s,
-                          factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 16 : 0);
+                          factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 32 : 0);
     });
   if (e == hipSuccess && factor_b) e = hipStreamWaitEvent(s, c->ev_f, 0);
   if (e != hipSuccess) return hip_fail(c, e, "E-step launch");

@@ -88,13 +88,16 @@ __global__ __launch_bounds__(256) void k_ms_load(int H, const float* __restrict_
                                                  double* __restrict__ M) {
   const double jitter = 1e-12 * (hdr->trB > 0.0 ? hdr->trB / H : 1.0);
   const int64_t HH = (int64_t)H * H;
+  // unconditional loads (upper-triangle element, both diagonals) so that
+  // the unrolled iterations keep their loads in flight together
+#pragma unroll 4
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < HH;
        e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e / H), j = (int)(e % H);
-    const bool ai = Bup[(int64_t)i * H + i] > 0.0f, aj = Bup[(int64_t)j * H + j] > 0.0f;
-    double v;
-    if (ai && aj) v = (i <= j) ? (double)Bup[(int64_t)i * H + j] : (double)Bup[(int64_t)j * H + i];
-    else v = (i == j) ? 1.0 : 0.0;
+    const float bii = Bup[(int64_t)i * H + i], bjj = Bup[(int64_t)j * H + j];
+    const float bu = Bup[(int64_t)min(i, j) * H + max(i, j)];
+    const bool ai = bii > 0.0f, aj = bjj > 0.0f;
+    double v = (ai && aj) ? (double)bu : ((i == j) ? 1.0 : 0.0);
     if (i == j && ai) v += jitter;
     M[e] = v;
   }
@@ -219,10 +222,26 @@ __global__ __launch_bounds__(256) void k_ms_syrk(int H, int kb, double* __restri
   }
   const int tj = t;
   const int i0 = k1 + 32 * ti, j0 = k1 + 32 * tj;
-  for (int e = threadIdx.x; e < 32 * NB; e += 256) {
+  // every load of the two 32 x 64 panels is issued before the first LDS
+  // store (clamped addresses, masked values): this kernel runs beside the
+  // HBM-bound statistics, where each dependent round trip costs microseconds
+  constexpr int PER = 32 * NB / 256;
+  double vi[PER], vj[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
     const int r = e / NB, c = e % NB;
-    Pi[r][c] = (i0 + r < H && c < nb) ? M[(int64_t)(i0 + r) * H + kb + c] : 0.0;
-    Pj[r][c] = (j0 + r < H && c < nb) ? M[(int64_t)(j0 + r) * H + kb + c] : 0.0;
+    const int cc = c < nb ? c : 0;
+    const double a = M[(int64_t)min(i0 + r, H - 1) * H + kb + cc];
+    const double b = M[(int64_t)min(j0 + r, H - 1) * H + kb + cc];
+    vi[k] = (i0 + r < H && c < nb) ? a : 0.0;
+    vj[k] = (j0 + r < H && c < nb) ? b : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    Pi[e / NB][e % NB] = vi[k];
+    Pj[e / NB][e % NB] = vj[k];
   }
   __syncthreads();
   const int r = threadIdx.x >> 3, cb = (threadIdx.x & 7) * 4;  // 32 rows x (8 x 4 cols)
@@ -454,8 +473,9 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
   const MstepWork w = carve_mstep(work, D, H);
   hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(1024), 0, st, H, B, w.hdr);
   const int64_t HH = (int64_t)H * H;
-  // few workgroups: when B is factored beside the A statistics only a few
-  // CUs are free
+  // at most 16 workgroups: when B is factored beside the A statistics only
+  // the CUs those leave out are free, and more workgroups than fit there
+  // wait for the statistics to end
   int64_t lb = (HH + 2047) / 2048;
   if (lb > 16) lb = 16;
   hipLaunchKernelGGL(k_ms_load, dim3((unsigned)lb), dim3(256), 0, st, H, B, w.hdr, w.M);
