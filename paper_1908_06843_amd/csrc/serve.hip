@@ -102,6 +102,7 @@ struct Batch {
   bool w_sel = false, w_sm = false, w_logL = false, w_flag = false, w_tm = false, w_tq = false;
   // layout inside the pool piece
   size_t o_Y, o_sel, o_bc, o_yy, o_sm, o_redo, o_cnt, o_logL, o_flag, o_tm, o_tq;
+  size_t o_end;  // end of the outputs (o_sel .. o_end holds all of them)
 };
 
 struct TableDev {
@@ -120,10 +121,13 @@ size_t layout_bytes(int64_t n, int Hp, int topk, int D, Batch* b) {
     return at;
   };
   const size_t N = (size_t)n, H1 = (size_t)Hp, K = (size_t)topk;
-  const size_t oY = take(N * D * 4), osel = take(N * H1 * 4), obc = take(N * H1 * 4),
-               oyy = take(N * 4), osm = take(N * H1 * 4), oredo = take(N * 4), ocnt = take(4),
-               ologL = take(N * 4), oflag = take(N), otm = take(N * K * 4 * 2),
-               otq = take(N * K * 4);
+  // inputs and scratch first, then the outputs back to back, so that one
+  // copy returns all of them
+  const size_t oY = take(N * D * 4), obc = take(N * H1 * 4), oyy = take(N * 4),
+               oredo = take(N * 4), ocnt = take(4), osel = take(N * H1 * 4),
+               osm = take(N * H1 * 4), ologL = take(N * 4), oflag = take(N),
+               otm = take(N * K * 4 * 2), otq = take(N * K * 4);
+  if (b) b->o_end = otq + N * K * 4;
   if (b) {
     b->o_Y = oY;
     b->o_sel = osel;
@@ -307,18 +311,12 @@ void launch(prosper_server* s, Batch* b) {
                           s->D, s->H, b->Hp, b->gamma, tab->count, tab->act, tab->sgn, s->prep,
                           sc, flag, logL, tm, tq, b->topk, nullptr, nullptr, nullptr, s->num_cu,
                           stm);
-  // outputs back to the pinned area
-  auto d2h = [&](size_t o, size_t n) {
-    if (e == hipSuccess && n) e = hipMemcpyAsync(pin + o, dev + o, n, hipMemcpyDeviceToHost, stm);
-  };
-  const size_t N = (size_t)b->n, Hp = (size_t)b->Hp, K = (size_t)b->topk;
-  const size_t tmw = (s->model == PROSPER_TSC) ? 2 : 1;
-  if (b->w_sel) d2h(b->o_sel, N * Hp * 4);
-  if (b->w_sm) d2h(b->o_sm, N * Hp * 4);
-  if (b->w_logL) d2h(b->o_logL, N * 4);
-  if (b->w_flag) d2h(b->o_flag, N);
-  if (b->w_tm) d2h(b->o_tm, N * K * 4 * tmw);
-  if (b->w_tq) d2h(b->o_tq, N * K * 4);
+  // outputs back to the pinned area: one copy over the contiguous output
+  // span (a few tens of bytes per row; fewer API calls on the scheduler
+  // thread matter more than the unwanted bytes)
+  if (e == hipSuccess && (b->w_sel || b->w_sm || b->w_logL || b->w_flag || b->w_tm || b->w_tq))
+    e = hipMemcpyAsync(pin + b->o_sel, dev + b->o_sel, b->o_end - b->o_sel,
+                       hipMemcpyDeviceToHost, stm);
   if (e == hipSuccess) {
     if (!s->ev_pool.empty()) {
       b->ev = s->ev_pool.back();
