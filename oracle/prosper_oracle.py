@@ -16,6 +16,8 @@ Table 1; truncated posteriors per the same section and the introduction):
     - BSC: s in {0,1}^H, Bernoulli(pi) prior, f = W s
     - TSC: s in {-1,0,1}^H, P(+-1) = pi/2, P(0) = 1 - pi, f = W s
     - MCA: s in {0,1}^H, Bernoulli(pi) prior, f_d = max_h s_h W_dh
+    - MMCA: s in {0,1}^H, Bernoulli(pi) prior, f_d = the s_h W_dh of
+      largest magnitude (ties to the lower h)
 * E-step with truncated posteriors: per data point a set I_n of H' latents is
   preselected ("Hprime" of the API section), the state set K_n holds every
   state whose support lies in I_n with at most gamma non-zero entries
@@ -29,7 +31,8 @@ Readings where the paper is silent (each listed in the design notes):
   canonical state order = (number of active slots, lexicographic slot
   tuple, TSC sign pattern in binary counting order);
   MCA M-step = hard-max responsibilities (limit of the smooth max), sigma
-  from the old W in the same sweep.
+  from the old W in the same sweep; MMCA takes the same M-step with the
+  responsibility given to the active latent of largest |W_dh|.
 
 Parity pins: see tests/test_oracle_*.py (brute force over all states with
 scipy's multivariate normal, closed forms at H = 1, MCA == BSC special cases,
@@ -50,14 +53,15 @@ import numpy as np
 from scipy.special import logsumexp
 
 __all__ = [
-    "BSC", "TSC", "MCA", "MODELS", "TIE_REL",
+    "BSC", "TSC", "MCA", "MMCA", "MODELS", "MAX_MODELS", "TIE_REL",
     "state_table", "state_masks", "log_prior", "superposition", "log_joint",
     "selection_scores", "preselect", "estep_point", "estep", "mstep",
     "em_run", "free_energy",
 ]
 
-BSC, TSC, MCA = "bsc", "tsc", "mca"
-MODELS = (BSC, TSC, MCA)
+BSC, TSC, MCA, MMCA = "bsc", "tsc", "mca", "mmca"
+MODELS = (BSC, TSC, MCA, MMCA)
+MAX_MODELS = (MCA, MMCA)  # non-linear superposition, responsibility M-step
 TIE_REL = 1e-6  # selection boundary flag band (relative, floor 1)
 
 
@@ -122,9 +126,14 @@ def log_prior(model: str, S: np.ndarray, pi: float) -> np.ndarray:
 
 
 def superposition(model: str, W: np.ndarray, S: np.ndarray) -> np.ndarray:
-    """f(Theta, s) for every row of S: W s (linear) or max_h s_h W_dh (MCA)."""
+    """f(Theta, s) for every row of S: W s (linear), max_h s_h W_dh (MCA) or
+    the s_h W_dh of largest magnitude, ties to the lower h (MMCA)."""
     if model == MCA:
         return (S[:, None, :] * W[None, :, :]).max(axis=2)
+    if model == MMCA:
+        SW = S[:, None, :] * W[None, :, :]                 # |K| x D x H
+        win = np.abs(SW).argmax(axis=2)                     # first maximum
+        return np.take_along_axis(SW, win[:, :, None], axis=2)[:, :, 0]
     return S @ W.T
 
 
@@ -199,10 +208,10 @@ def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: floa
         order = np.lexsort((idx, -q))[:topk]
         out["top_index"] = order
         out["top_q"] = q[order]
-    if model == MCA:
+    if model in MAX_MODELS:
         # responsibilities: R[d, j] = sum_s q(s) [slot j is the lowest-index
-        # active slot attaining the max of W_d over the active set, and that
-        # max is > 0]
+        # active slot attaining the max of W_d (MCA) or of |W_d| (MMCA) over
+        # the active set, and that max is > 0]
         Wc = W[:, sel]
         R = np.zeros((W.shape[0], Hp))
         res = y[None, :] - superposition(model, W, S)
@@ -210,6 +219,8 @@ def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: floa
             if not slots:
                 continue
             sub = Wc[:, list(slots)]
+            if model == MMCA:
+                sub = np.abs(sub)
             am = np.argmax(sub, axis=1)
             mx = sub[np.arange(sub.shape[0]), am]
             pos = mx > 0
@@ -226,8 +237,8 @@ def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
     Returns per-point arrays (sel, flagged, logL, s_mean, ss_mean, k_mean,
     top_index, top_q) and the sums
       BSC/TSC: A = sum y <s>^T (D x H), B = sum <ss^T> (H x H)
-      MCA:     A = sum R * y (D x H),   B = sum R (D x H)
-      scal = [sum <k>, sum logL, sum ||y||^2, sum <||y - f(s)||^2> (MCA), N]
+      MCA/MMCA: A = sum R * y (D x H),  B = sum R (D x H)
+      scal = [sum <k>, sum logL, sum ||y||^2, sum <||y - f(s)||^2> (MCA/MMCA), N]
     """
     Y = np.asarray(Y, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
@@ -243,7 +254,7 @@ def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
     top_index = np.zeros((N, topk), dtype=np.int64)
     top_q = np.zeros((N, topk))
     A = np.zeros((D, H))
-    B = np.zeros((H, H)) if model != MCA else np.zeros((D, H))
+    B = np.zeros((H, H)) if model not in MAX_MODELS else np.zeros((D, H))
     res_sum = 0.0
     post = []
     for n in range(N):
@@ -253,7 +264,7 @@ def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
         if topk:
             top_index[n], top_q[n] = p["top_index"], p["top_q"]
         c = p["sel"]
-        if model == MCA:
+        if model in MAX_MODELS:
             A[:, c] += p["R"] * Y[n][:, None]
             B[:, c] += p["R"]
             res_sum += p["res_mean"]
@@ -286,7 +297,7 @@ def mstep(model: str, Y: np.ndarray, W_old: np.ndarray, est: Dict,
     BSC/TSC: W = A B^-1 on the latents with B_hh > 0 (others keep their old
     column); pi = sum<k>/(N H); sigma^2 = sum_n sum_s q ||y - W_new s||^2/(N D)
     as a direct second sweep over each K_n (needs keep_posterior=True).
-    MCA: W_dh = sum R y / sum R (zero denominator keeps the old value);
+    MCA/MMCA: W_dh = sum R y / sum R (zero denominator keeps the old value);
     pi as BSC; sigma^2 = sum_n sum_s q ||y - f_{W_old}(s)||^2 / (N D).
     """
     Y = np.asarray(Y, dtype=np.float64)
@@ -296,7 +307,7 @@ def mstep(model: str, Y: np.ndarray, W_old: np.ndarray, est: Dict,
     A, B, scal = est["A"], est["B"], est["scal"]
     pi_new = scal[0] / (N * H)
     W_new = W_old.copy()
-    if model == MCA:
+    if model in MAX_MODELS:
         pos = B > 0
         W_new[pos] = A[pos] / B[pos]
         sigma2 = scal[3] / (N * D)
@@ -325,7 +336,7 @@ def em_run(model: str, Y: np.ndarray, W0: np.ndarray, pi0: float, sigma0: float,
     W, pi, sigma = np.asarray(W0, dtype=np.float64), float(pi0), float(sigma0)
     F = []
     for it in range(iters):
-        est = estep(model, Y, W, pi, sigma, Hp, gamma, keep_posterior=(model != MCA))
+        est = estep(model, Y, W, pi, sigma, Hp, gamma, keep_posterior=(model not in MAX_MODELS))
         F.append(free_energy(est))
         W, pi, sigma = mstep(model, Y, W, est)
         if callback is not None:
