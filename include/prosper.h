@@ -12,6 +12,8 @@
  *   PROSPER_BSC  s in {0,1}^H,    Bernoulli(pi),           f = W s
  *   PROSPER_TSC  s in {-1,0,1}^H, P(+-1) = pi/2 each,      f = W s
  *   PROSPER_MCA  s in {0,1}^H,    Bernoulli(pi),           f_d = max_h s_h W_dh
+ *   PROSPER_MMCA s in {0,1}^H,    Bernoulli(pi),           f_d = the s_h W_dh of largest
+ *                magnitude (lower h on a tie); statistics and M-step as MCA
  *
  * Truncated posteriors (same section): for each data point y_n the library
  * preselects H' latents I_n (the "Hprime" argument of the API section) and
@@ -52,7 +54,7 @@ typedef enum {
     PROSPER_ETIMEDOUT = -6  /* serving wait ran out of time; request still live */
 } prosper_status;
 
-typedef enum { PROSPER_BSC = 0, PROSPER_TSC = 1, PROSPER_MCA = 2 } prosper_model;
+typedef enum { PROSPER_BSC = 0, PROSPER_TSC = 1, PROSPER_MCA = 2, PROSPER_MMCA = 3 } prosper_model;
 
 /* Precision of the N x D x H projection contraction (W^T y for all latents).
  *  PROSPER_FP32: FP32 MFMA (v_mfma_f32_16x16x4_f32), FP32 accumulation.

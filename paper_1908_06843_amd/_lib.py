@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # PROSPER_LIB may name another build of the same library (e.g. an instrumented one)
 LIB_PATH = os.environ.get("PROSPER_LIB") or os.path.join(_HERE, "libprosper.so")
 
-MODELS = {"bsc": 0, "tsc": 1, "mca": 2}
+MODELS = {"bsc": 0, "tsc": 1, "mca": 2, "mmca": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY",
           -5: "ENOTFOUND", -6: "ETIMEDOUT"}

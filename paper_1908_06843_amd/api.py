@@ -77,9 +77,9 @@ def _dev_f32(name: str, t: torch.Tensor) -> torch.Tensor:
 
 
 def new_acc(model: str, D: int, H: int, device=None) -> Dict[str, torch.Tensor]:
-    """Zeroed M-step accumulators (A: D x H, B: H x H or D x H for MCA, scal: 5 doubles)."""
+    """Zeroed M-step accumulators (A: D x H, B: H x H, or D x H for MCA/MMCA, scal: 5 doubles)."""
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-    Bshape = (D, H) if model == "mca" else (H, H)
+    Bshape = (D, H) if model in ("mca", "mmca") else (H, H)
     return {"A": torch.zeros((D, H), dtype=torch.float32, device=dev),
             "B": torch.zeros(Bshape, dtype=torch.float32, device=dev),
             "scal": torch.zeros(5, dtype=torch.float64, device=dev)}

@@ -142,7 +142,7 @@ void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
 
 prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* out,
                             std::string* msg) {
-  if (model != PROSPER_BSC && model != PROSPER_TSC && model != PROSPER_MCA) {
+  if (model != PROSPER_BSC && model != PROSPER_TSC && !is_max_model(model)) {
     if (msg) *msg = "unknown model";
     return PROSPER_EINVAL;
   }
@@ -178,7 +178,7 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "args is NULL";
     return PROSPER_EINVAL;
   }
-  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_MCA) {
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && !is_max_model(a->model)) {
     *msg = "unknown model";
     return PROSPER_EINVAL;
   }
@@ -228,7 +228,7 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "unknown flag bits";
     return PROSPER_EINVAL;
   }
-  if ((a->flags & PROSPER_FLAG_FACTOR_B) && (!a->accumulate || a->model == PROSPER_MCA)) {
+  if ((a->flags & PROSPER_FLAG_FACTOR_B) && (!a->accumulate || is_max_model(a->model))) {
     *msg = "PROSPER_FLAG_FACTOR_B needs accumulate = 1 and a linear model (BSC/TSC)";
     return PROSPER_EINVAL;
   }
@@ -239,7 +239,7 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "topk larger than the truncated state set";
     return PROSPER_EINVAL;
   }
-  if (a->model == PROSPER_MCA) {
+  if (is_max_model(a->model)) {
     const size_t lds = states_max_lds_bytes(a->Hprime, a->D, ns, a->accumulate != 0);
     if (lds > 150 * 1024) {
       *msg = "MCA shape (Hprime x D and |K|) exceeds the per-workgroup LDS of this build";
@@ -251,7 +251,7 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
 }
 
 prosper_status get_table(prosper_ctx* c, int model, int Hp, int gamma, Table** out) {
-  auto key = std::make_tuple(model == PROSPER_MCA ? PROSPER_BSC : model, Hp, gamma);
+  auto key = std::make_tuple(is_max_model(model) ? PROSPER_BSC : model, Hp, gamma);
   auto it = c->tables.find(key);
   if (it != c->tables.end()) {
     *out = &it->second;
@@ -364,8 +364,8 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
   const int Dp = padded_depth(D);
   hipError_t e = launch_project_select(model, prec, Y, N, D, Dp, H, Hp, p, sc, flagged, scal, s);
   if (e != hipSuccess) return e;
-  if (model == PROSPER_MCA)
-    return launch_states_max(Hp, gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL, top_mask, top_q,
+  if (is_max_model(model))
+    return launch_states_max(model, Hp, gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL, top_mask, top_q,
                              topk, A, B, scal, s);
   int tree_blocks = 0;
   e = launch_states_lin(model, Hp, gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask,
@@ -536,7 +536,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   const int Hpad = (H + 63) / 64 * 64;
   const int defer_cap = project_defer_capacity(N, H, Hp);
   add((size_t)defer_cap * (Hpad + 8) * 4);
-  const bool lin_acc = a->accumulate && model != PROSPER_MCA;
+  const bool lin_acc = a->accumulate && !is_max_model(model);
   const size_t npairs = (size_t)Hp * (Hp + 1) / 2;
   StatsPlan plan = stats_plan(N, D, H, c->num_cu);
   const bool tree_acc = lin_acc && a->topk == 0 && has_tree_kernel(model, Hp, a->gamma) &&
@@ -609,15 +609,15 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
       return launch_project_select(model, prec, Y, N, D, Dp2, H, Hp, p, sc, flagged, scal, s);
     });
   if (e == hipSuccess)
-    e = timed(c, model == PROSPER_MCA ? "states_max" : "states_lin", s, [&] {
-      if (model == PROSPER_MCA)
-        return launch_states_max(Hp, a->gamma, N, D, Dp2, H, ns, tab->act, Y, p, sc, logL,
+    e = timed(c, is_max_model(model) ? "states_max" : "states_lin", s, [&] {
+      if (is_max_model(model))
+        return launch_states_max(model, Hp, a->gamma, N, D, Dp2, H, ns, tab->act, Y, p, sc, logL,
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
       return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab->act, tab->sgn, p, sc, logL,
                                top_mask, top_q, a->topk, Aacc != nullptr, Bacc, scal, c->num_cu,
                                &tree_blocks, s);
     });
-  if (e == hipSuccess && Aacc && model != PROSPER_MCA)
+  if (e == hipSuccess && Aacc && !is_max_model(model))
     e = timed(c, "stats", s, [&] {
       return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s,
                           factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 32 : 0);
@@ -638,7 +638,7 @@ prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prospe
                              const float* W_old, float* W_new, double* theta_new, void* stream) {
   if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
   if (!a) return fail(c, PROSPER_EINVAL, "args is NULL");
-  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_MCA)
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && !is_max_model(a->model))
     return fail(c, PROSPER_EINVAL, "unknown model");
   if (a->D < 1 || a->D > PROSPER_MAX_D || a->H < 1 || a->H > PROSPER_MAX_H)
     return fail(c, PROSPER_EINVAL, "D or H out of range");

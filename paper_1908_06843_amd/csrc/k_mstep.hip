@@ -454,7 +454,7 @@ __global__ void k_mstep_scalars_mca(int D, int H, const double* __restrict__ sca
 }
 
 size_t mstep_workspace_bytes(int model, int D, int H) {
-  if (model == PROSPER_MCA) return 256;
+  if (is_max_model(model)) return 256;
   return 256 + round_up((size_t)H * H * 8, 256) + round_up((size_t)H * 8, 256) +
          round_up((size_t)D * 8, 256);
 }
@@ -468,7 +468,7 @@ static void launch_solve(int D, int H, const float* A, const float* B, const Mst
 
 hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* work,
                                hipStream_t st) {
-  if (model == PROSPER_MCA) return hipSuccess;
+  if (is_max_model(model)) return hipSuccess;
   if (H > 16 * 64) return hipErrorInvalidValue;
   const MstepWork w = carve_mstep(work, D, H);
   hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(1024), 0, st, H, B, w.hdr);
@@ -496,7 +496,7 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
 hipError_t launch_mstep_solve(int model, int D, int H, const float* A, const float* B,
                               const double* scal, const float* W_old, float* W_new,
                               double* theta_new, void* work, hipStream_t st) {
-  if (model == PROSPER_MCA) {
+  if (is_max_model(model)) {
     const int64_t n = (int64_t)D * H;
     hipLaunchKernelGGL(k_mstep_mca, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, H, A,
                        B, W_old, W_new);

@@ -256,7 +256,7 @@ PROSPER_TREE_SHAPES(X)
 
 bool has_tree_kernel(int model, int Hp, int gamma) {
 #define X(T, HP, GM) \
-  if ((model == PROSPER_TSC) == T && model != PROSPER_MCA && Hp == HP && gamma == GM) return true;
+  if ((model == PROSPER_TSC) == T && !is_max_model(model) && Hp == HP && gamma == GM) return true;
   PROSPER_TREE_SHAPES(X)
 #undef X
   return false;

@@ -22,6 +22,15 @@
 //             max_{j in s} P_dj, and that max is > 0]
 // accumulated as A_num[d][c_j] += R y_d and B_den[d][c_j] += R, plus
 // sum_s q(s) ||y - f(s)||^2 for the noise update.
+//
+// MMCA (MAG = true): f_d(s) is the s_h W_dh of largest magnitude, the lower
+// slot on equal magnitudes, and 0 for the zero state; P is W itself (no clamp).
+// The responsibility of pixel d goes to the active slot of largest |P_dj|
+// when that magnitude is > 0; statistics and M-step are those of MCA.
+// With both signs in W every pixel of an active state differs from y, so the
+// walk sums the residual relative to the zero state, sum_d mu_d (mu_d - 2 y_d),
+// which stays small where ||y||^2 would dominate FP32 rounding; lam ||y||^2
+// (reduced in FP64) is added back to logL and to the expected residual.
 #include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
@@ -29,6 +38,7 @@ namespace prosper {
 
 static constexpr int MCA_ND = 16;  // pixels per lane (D <= 1024)
 
+template <bool MAG>
 __global__ __launch_bounds__(64) void k_states_max(
     const float* __restrict__ Y, int64_t N, int D, int Dp, int H, int Hp, int64_t nstates,
     const uint32_t* __restrict__ tab_act, const float* __restrict__ Pt32,
@@ -77,15 +87,23 @@ __global__ __launch_bounds__(64) void k_states_max(
           for (int i = 0; i < MCA_ND; ++i) {
             const int d = lane + 64 * i;
             if (i < nd && d < D) {
-              float mu = floor0 ? 0.0f : -INFINITY;
+              float mu = (MAG || floor0) ? 0.0f : -INFINITY;
               uint32_t rem = act;
               while (rem) {
                 const int j = __ffs(rem) - 1;
                 rem &= rem - 1u;
-                mu = fmaxf(mu, Pc[j * D + d]);
+                const float v = Pc[j * D + d];
+                if (MAG)
+                  mu = (fabsf(v) > fabsf(mu)) ? v : mu;
+                else
+                  mu = fmaxf(mu, v);
               }
-              const float r = yv[i] - mu;
-              part = __builtin_fmaf(r, r, part);
+              if (MAG) {
+                part = __builtin_fmaf(mu, mu - 2.0f * yv[i], part);
+              } else {
+                const float r = yv[i] - mu;
+                part = __builtin_fmaf(r, r, part);
+              }
             }
           }
         }
@@ -166,13 +184,20 @@ __global__ __launch_bounds__(64) void k_states_max(
       kmean += part;
       if (lane == 0) s_mean[n * Hp + j] = part;
     }
-    const float resid = wave_sum(res);  // <||y - f(s)||^2>
-    const double lL = th->c0 + 0.6931471805599453 * ((double)m + (double)log2f(Z));
+    const float resid = wave_sum(res);  // <||y - f(s)||^2>, relative to ||y||^2 if MAG
+    double yy_n = 0.0;
+    if (MAG) {
+#pragma unroll
+      for (int i = 0; i < MCA_ND; ++i) yy_n += (double)yv[i] * (double)yv[i];
+      for (int w = 32; w >= 1; w >>= 1) yy_n += __shfl_xor(yy_n, w, 64);
+    }
+    const double lL = th->c0 + 0.6931471805599453 * ((double)m + (double)log2f(Z) -
+                                                     (double)lam2 * yy_n);
     if (lane == 0) {
       if (logL) logL[n] = (float)lL;
       acc_k += kmean;
       acc_l += lL;
-      acc_r += resid;
+      acc_r += (double)resid + yy_n;
     }
     // ---- responsibilities
     if (A_num) {
@@ -184,13 +209,13 @@ __global__ __launch_bounds__(64) void k_states_max(
         for (int i = 0; i < MCA_ND; ++i) {
           const int d = lane + 64 * i;
           if (i < nd && d < D) {
-            float best = -INFINITY;
+            float best = MAG ? 0.0f : -INFINITY;
             int bj = -1;
             uint32_t rem = act;
             while (rem) {
               const int j = __ffs(rem) - 1;
               rem &= rem - 1u;
-              const float v = Pc[j * D + d];
+              const float v = MAG ? fabsf(Pc[j * D + d]) : Pc[j * D + d];
               if (v > best) {
                 best = v;
                 bj = j;
@@ -228,7 +253,7 @@ size_t states_max_lds_bytes(int Hp, int D, int64_t nstates, bool acc) {
   return ((size_t)Hp * D + 2 * (size_t)((nstates + 3) & ~(int64_t)3) + (acc ? (size_t)Hp * D : 0)) * 4;
 }
 
-hipError_t launch_states_max(int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
+hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
                              const uint32_t* tab_act, const float* Y, const Prepared& p,
                              const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, float* A_num, float* B_den, double* scal,
@@ -236,15 +261,17 @@ hipError_t launch_states_max(int Hp, int gamma, int64_t N, int D, int Dp, int H,
   (void)gamma;
   if (N <= 0) return hipSuccess;
   const size_t lds = states_max_lds_bytes(Hp, D, nstates, A_num != nullptr);
-  static size_t configured = 0;
-  if (lds > configured) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_states_max),
+  const bool mag = model == PROSPER_MMCA;
+  static size_t configured[2] = {0, 0};
+  const auto kern = mag ? k_states_max<true> : k_states_max<false>;
+  if (lds > configured[mag]) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    configured = lds;
+    configured[mag] = lds;
   }
   int64_t blocks = N < 8192 ? N : 8192;
-  hipLaunchKernelGGL(k_states_max, dim3((unsigned)blocks), dim3(64), lds, st, Y, N, D, Dp, H, Hp,
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, st, Y, N, D, Dp, H, Hp,
                      nstates, tab_act, p.Pt32, s.sel, s.yy, p.theta, s.s_mean, logL, top_mask,
                      top_q, topk, A_num, B_den, scal);
   return hipGetLastError();

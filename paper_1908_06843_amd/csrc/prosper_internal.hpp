@@ -128,8 +128,10 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
                              uint32_t* top_mask, float* top_q, int topk, bool acc,
                              float* acc_B, double* scal, int num_cu, int* tree_blocks,
                              hipStream_t st);
-// MCA state walk (max superposition).
-hipError_t launch_states_max(int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
+// Max-superposition models: MCA and MMCA share the walk, statistics and M-step.
+inline bool is_max_model(int m) { return m == PROSPER_MCA || m == PROSPER_MMCA; }
+// MCA/MMCA state walk (max / largest-magnitude superposition).
+hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
                              const uint32_t* tab_act, const float* Y, const Prepared& p,
                              const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, float* A_num, float* B_den, double* scal,

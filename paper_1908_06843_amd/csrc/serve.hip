@@ -428,7 +428,7 @@ prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_devi
                              int32_t n_streams, int32_t queue_capacity, prosper_server** out) {
   if (!ctx || !W || !out) return PROSPER_EINVAL;
   *out = nullptr;
-  if (model != PROSPER_BSC && model != PROSPER_TSC && model != PROSPER_MCA) return PROSPER_EINVAL;
+  if (model != PROSPER_BSC && model != PROSPER_TSC && !is_max_model(model)) return PROSPER_EINVAL;
   if (precision != PROSPER_FP32 && precision != PROSPER_BF16) return PROSPER_EINVAL;
   if (D < 1 || D > PROSPER_MAX_D || H < 1 || H > PROSPER_MAX_H) return PROSPER_EINVAL;
   if (!(pi > 0.0 && pi < 1.0) || !(sigma > 0.0)) return PROSPER_EINVAL;
