@@ -184,13 +184,24 @@ def preselect(r: np.ndarray, Hp: int, tie_rel: float = TIE_REL) -> Tuple[np.ndar
 # E-step
 # --------------------------------------------------------------------------
 def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
-                Hp: int, gamma: int, topk: int = 0, tab=None) -> Dict:
-    """Truncated posterior of one data point (all float64)."""
+                Hp: int, gamma: int, topk: int = 0, tab=None, sel=None) -> Dict:
+    """Truncated posterior of one data point (all float64).
+
+    `sel` (optional, H' distinct latents) replaces the preselected set I_n;
+    it is meant for near-tie points, where more than one candidate set is a
+    correct preselection and the posterior on another valid one is wanted.
+    The scores and the near-tie flag are still those of the data point."""
     y = np.asarray(y, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     H = W.shape[1]
     r = selection_scores(model, y, W)
-    sel, flagged = preselect(r, Hp)
+    auto, flagged = preselect(r, Hp)
+    if sel is None:
+        sel = auto
+    else:
+        sel = np.sort(np.asarray(sel, dtype=np.int64))
+        if sel.shape != (Hp,) or len(set(sel.tolist())) != Hp or sel[0] < 0 or sel[-1] >= H:
+            raise ValueError("sel must hold H' distinct latent indices")
     if tab is None:
         tab = state_table(model, Hp, gamma)
     S = _embed(tab, sel, H)                      # |K| x H
@@ -231,8 +242,11 @@ def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: floa
 
 
 def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
-          Hp: int, gamma: int, topk: int = 0, keep_posterior: bool = False) -> Dict:
+          Hp: int, gamma: int, topk: int = 0, keep_posterior: bool = False,
+          sel: np.ndarray = None) -> Dict:
     """Truncated E-step over all points, plus the M-step accumulators.
+    `sel` (optional, N x H') replaces the preselection point by point (see
+    estep_point).
 
     Returns per-point arrays (sel, flagged, logL, s_mean, ss_mean, k_mean,
     top_index, top_q) and the sums
@@ -244,6 +258,7 @@ def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
     W = np.asarray(W, dtype=np.float64)
     N, D = Y.shape
     H = W.shape[1]
+    forced = sel
     tab = state_table(model, Hp, gamma)
     sel = np.zeros((N, Hp), dtype=np.int64)
     flagged = np.zeros(N, dtype=bool)
@@ -258,7 +273,8 @@ def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
     res_sum = 0.0
     post = []
     for n in range(N):
-        p = estep_point(model, Y[n], W, pi, sigma, Hp, gamma, topk, tab)
+        p = estep_point(model, Y[n], W, pi, sigma, Hp, gamma, topk, tab,
+                        None if forced is None else forced[n])
         sel[n], flagged[n], logL[n] = p["sel"], p["flagged"], p["logL"]
         s_mean[n], ss_mean[n], k_mean[n] = p["s_mean"], p["ss_mean"], p["k_mean"]
         if topk:
