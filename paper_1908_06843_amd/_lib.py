@@ -11,8 +11,8 @@ import os
 from typing import Optional
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# PROSPER_LIB may name another build of the same library (e.g. an instrumented one)
-LIB_PATH = os.environ.get("PROSPER_LIB") or os.path.join(_HERE, "libprosper.so")
+# always the in-tree build: tests and the benchmark must exercise this library
+LIB_PATH = os.path.join(_HERE, "libprosper.so")
 
 MODELS = {"bsc": 0, "tsc": 1, "mca": 2, "mmca": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}

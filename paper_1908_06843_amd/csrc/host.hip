@@ -105,6 +105,23 @@ hipError_t ensure(DevBuf& b, size_t bytes) {
 }  // namespace
 
 namespace prosper {
+prosper_status set_error(prosper_status st, const std::string& msg) {
+  g_tls_err = msg;
+  return st;
+}
+
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = done[kernel];
+  if (have >= bytes) return hipSuccess;
+  hipError_t e =
+      hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) have = bytes;
+  return e;
+}
+
 // Canonical enumeration: k ascending, slot tuples lexicographic, TSC sign
 // codes counting up (bit i of the code = sign of the i-th active slot).
 void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
@@ -290,6 +307,7 @@ size_t prep_bytes(int Dp, int H, int prec) {
   add((size_t)H * 4);
   add((size_t)H * 4);
   add(4);
+  add((size_t)Dp * 4);
   add(sizeof(Theta));
   return b + 256;
 }
@@ -304,6 +322,7 @@ Prepared carve_prep(void* base, int Dp, int H, int prec) {
   p.hn_hi = cv.take<float>(H);
   p.hn_lo = cv.take<float>(H);
   p.pnorm = cv.take<float>(1);
+  p.wmax = cv.take<float>(Dp);
   p.theta = cv.take<Theta>(1);
   return p;
 }
@@ -325,7 +344,7 @@ hipEvent_t prof_event(prosper_ctx* c) {
 // Runs `launch` between two events on stream s when profiling is enabled.
 template <typename F>
 hipError_t timed(prosper_ctx* c, const char* name, hipStream_t s, F&& launch) {
-  if (!c->prof) return launch();
+  if (!c || !c->prof) return launch();
   hipEvent_t a = prof_event(c), b = prof_event(c);
   hipEventRecord(a, s);
   hipError_t e = launch();
@@ -374,6 +393,136 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
     e = launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, A, B, s, StatsHook(), 0);
   return e;
 }
+}  // namespace prosper
+
+namespace prosper {
+
+// Argument checks shared by the E-step entry points.
+prosper_status check_estep(const prosper_args* a, const float* Y, const float* W,
+                           const prosper_point_out* out, const prosper_acc* acc,
+                           std::string* msg, int64_t* ns) {
+  prosper_status st = validate(a, msg, ns);
+  if (st != PROSPER_OK) return st;
+  if (a->N == 0) return PROSPER_OK;
+  if (!Y || !W) {
+    *msg = "Y or W is NULL";
+    return PROSPER_EINVAL;
+  }
+  if (a->accumulate && (!acc || !acc->A || !acc->B || !acc->scal)) {
+    *msg = "accumulate=1 needs acc->A, acc->B and acc->scal";
+    return PROSPER_EINVAL;
+  }
+  if (a->topk > 0 && out && !out->top_mask && !out->top_q) {
+    *msg = "topk > 0 needs top_mask or top_q";
+    return PROSPER_EINVAL;
+  }
+  return PROSPER_OK;
+}
+
+// num_cu sizes the statistics partials (one per walk / statistics
+// workgroup); defer_cap is the length of the projection's deferral list.
+EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int num_cu,
+                       int defer_cap) {
+  EstepLayout L;
+  const int64_t N = a->N;
+  const int D = a->D, H = a->H, Hp = a->Hprime;
+  L.need_sel = !(out && out->sel);
+  L.need_sm = !(out && out->s_mean);
+  L.Hpad = (H + 63) / 64 * 64;
+  L.defer_cap = defer_cap;
+  L.lin_acc = a->accumulate && !is_max_model(a->model);
+  L.npairs = (size_t)Hp * (Hp + 1) / 2;
+  L.plan = stats_plan(N, D, H, num_cu);
+  L.tree_acc = L.lin_acc && a->topk == 0 && has_tree_kernel(a->model, Hp, a->gamma) &&
+               (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
+  L.partB_floats = L.tree_acc ? (size_t)num_cu * stats_bslice_floats() : L.plan.partB_floats;
+  size_t sb = 0;
+  auto add = [&](size_t n) { sb = ((sb + 255) & ~(size_t)255) + n; };
+  add(L.need_sel ? (size_t)N * Hp * 4 : 0);
+  add((size_t)N * Hp * 4);
+  add((size_t)N * 4);
+  add(L.need_sm ? (size_t)N * Hp * 4 : 0);
+  add((size_t)N * 4);
+  add(8);
+  add((size_t)defer_cap * (L.Hpad + 8) * 4);
+  add(L.lin_acc && !L.tree_acc ? L.npairs * N * 4 : 0);
+  add(L.lin_acc ? L.plan.partA_floats * 4 : 0);
+  add(L.lin_acc ? L.partB_floats * 4 : 0);
+  L.bytes = sb;
+  return L;
+}
+
+Scratch carve_estep(void* base, const EstepLayout& L, const prosper_args* a,
+                    const prosper_point_out* out) {
+  const int64_t N = a->N;
+  const int Hp = a->Hprime;
+  Carve cv{reinterpret_cast<char*>(base)};
+  Scratch sc;
+  int32_t* sel_ws = cv.take<int32_t>(L.need_sel ? (size_t)N * Hp : 0);
+  sc.bc = cv.take<float>((size_t)N * Hp);
+  sc.yy = cv.take<float>((size_t)N);
+  float* sm_ws = cv.take<float>(L.need_sm ? (size_t)N * Hp : 0);
+  sc.redo_list = cv.take<int32_t>((size_t)N);
+  sc.redo_count = cv.take<int32_t>(2);
+  sc.defer_count = sc.redo_count + 1;
+  sc.defer = cv.take<float>((size_t)L.defer_cap * (L.Hpad + 8));
+  sc.defer_cap = L.defer_cap;
+  sc.ss = cv.take<float>(L.lin_acc && !L.tree_acc ? L.npairs * N : 0);
+  if (!(L.lin_acc && !L.tree_acc)) sc.ss = nullptr;
+  sc.partA = cv.take<float>(L.lin_acc ? L.plan.partA_floats : 0);
+  sc.partB = cv.take<float>(L.lin_acc ? L.partB_floats : 0);
+  sc.plan = L.plan;
+  sc.sel = L.need_sel ? sel_ws : out->sel;
+  sc.s_mean = L.need_sm ? sm_ws : out->s_mean;
+  return sc;
+}
+
+// Parameter prep, projection + preselection, state walk and statistics of one
+// E-step on stream s.  c may be NULL (no profiling).  after_B runs once B is
+// complete; reserve_cu CUs are left free for work it forks.
+hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, const float* W,
+                         const prosper_point_out* out, const prosper_acc* acc, hipStream_t s,
+                         const Prepared& p, const Scratch& sc, const uint32_t* tab_act,
+                         const uint32_t* tab_sgn, int64_t ns, int num_cu,
+                         const StatsHook& after_B, int reserve_cu) {
+  const int model = a->model, prec = a->precision;
+  const int64_t N = a->N;
+  const int D = a->D, H = a->H, Hp = a->Hprime;
+  const int Dp = padded_depth(D);
+  uint8_t* flagged = out ? out->flagged : nullptr;
+  float* logL = out ? out->logL : nullptr;
+  uint32_t* top_mask = out ? out->top_mask : nullptr;
+  float* top_q = out ? out->top_q : nullptr;
+  float* Aacc = a->accumulate ? acc->A : nullptr;
+  float* Bacc = a->accumulate ? acc->B : nullptr;
+  double* scal = a->accumulate ? acc->scal : nullptr;
+  int tree_blocks = 0;
+  hipError_t e = timed(c, "prep", s, [&] {
+    hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
+                                      sc.redo_count, s, sc.defer_count);
+    return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp, p, s) : e2;
+  });
+  if (e == hipSuccess)
+    e = timed(c, "project_select", s, [&] {
+      return launch_project_select(model, prec, Y, N, D, Dp, H, Hp, p, sc, flagged, scal, s);
+    });
+  if (e == hipSuccess)
+    e = timed(c, is_max_model(model) ? "states_max" : "states_lin", s, [&] {
+      if (is_max_model(model))
+        return launch_states_max(model, Hp, a->gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL,
+                                 top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
+      return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL,
+                               top_mask, top_q, a->topk, Aacc != nullptr, Bacc, scal, num_cu,
+                               &tree_blocks, s);
+    });
+  if (e == hipSuccess && Aacc && !is_max_model(model))
+    e = timed(c, "stats", s, [&] {
+      return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s, after_B,
+                          reserve_cu);
+    });
+  return e;
+}
+
 }  // namespace prosper
 
 // ======================================================================= ABI
@@ -496,20 +645,14 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
   std::string msg;
   int64_t ns = 0;
-  prosper_status st = validate(a, &msg, &ns);
+  prosper_status st = check_estep(a, Y, W, out, acc, &msg, &ns);
   if (st != PROSPER_OK) return fail(c, st, msg);
   if (a->N == 0) return PROSPER_OK;
-  if (!Y || !W) return fail(c, PROSPER_EINVAL, "Y or W is NULL");
-  if (a->accumulate && (!acc || !acc->A || !acc->B || !acc->scal))
-    return fail(c, PROSPER_EINVAL, "accumulate=1 needs acc->A, acc->B and acc->scal");
-  if (a->topk > 0 && out && !out->top_mask && !out->top_q)
-    return fail(c, PROSPER_EINVAL, "topk > 0 needs top_mask or top_q");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
 
   const int model = a->model, prec = a->precision;
-  const int64_t N = a->N;
   const int D = a->D, H = a->H, Hp = a->Hprime;
   const int Dp = padded_depth(D);
 
@@ -521,66 +664,12 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "workspace (parameters) allocation failed");
   Prepared p = carve_prep(c->prep.p, Dp, H, prec);
 
-  const bool need_sel = !(out && out->sel);
-  const bool need_sm = !(out && out->s_mean);
-  size_t sb = 0;
-  auto add = [&](size_t n) { sb = ((sb + 255) & ~(size_t)255) + n; };
-  add(need_sel ? (size_t)N * Hp * 4 : 0);
-  add((size_t)N * Hp * 4);
-  add((size_t)N * 4);
-  add(need_sm ? (size_t)N * Hp * 4 : 0);
-  add((size_t)N * 4);
-  add(8);
-  // deferral list of the projection's exact selections (lane-per-point
-  // selection only); points beyond it are selected inside the projection
-  const int Hpad = (H + 63) / 64 * 64;
-  const int defer_cap = project_defer_capacity(N, H, Hp);
-  add((size_t)defer_cap * (Hpad + 8) * 4);
-  const bool lin_acc = a->accumulate && !is_max_model(model);
-  const size_t npairs = (size_t)Hp * (Hp + 1) / 2;
-  StatsPlan plan = stats_plan(N, D, H, c->num_cu);
-  const bool tree_acc = lin_acc && a->topk == 0 && has_tree_kernel(model, Hp, a->gamma) &&
-                        (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
-  const size_t partB_floats =
-      tree_acc ? (size_t)c->num_cu * stats_bslice_floats() : plan.partB_floats;
-  add(lin_acc && !tree_acc ? npairs * N * 4 : 0);
-  add(lin_acc ? plan.partA_floats * 4 : 0);
-  add(lin_acc ? partB_floats * 4 : 0);
-  e = ensure(c->scratch, sb + 256);
+  const EstepLayout L =
+      plan_estep(a, out, c->num_cu, project_defer_capacity(a->N, H, Hp));
+  e = ensure(c->scratch, L.bytes + 256);
   if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "workspace (per point) allocation failed");
-  Carve cv{reinterpret_cast<char*>(c->scratch.p)};
-  Scratch sc;
-  int32_t* sel_ws = cv.take<int32_t>(need_sel ? (size_t)N * Hp : 0);
-  sc.bc = cv.take<float>((size_t)N * Hp);
-  sc.yy = cv.take<float>((size_t)N);
-  float* sm_ws = cv.take<float>(need_sm ? (size_t)N * Hp : 0);
-  sc.redo_list = cv.take<int32_t>((size_t)N);
-  sc.redo_count = cv.take<int32_t>(2);
-  sc.defer_count = sc.redo_count + 1;
-  sc.defer = cv.take<float>((size_t)defer_cap * (Hpad + 8));
-  sc.defer_cap = defer_cap;
-  sc.ss = cv.take<float>(lin_acc && !tree_acc ? npairs * N : 0);
-  if (!(lin_acc && !tree_acc)) sc.ss = nullptr;
-  sc.partA = cv.take<float>(lin_acc ? plan.partA_floats : 0);
-  sc.partB = cv.take<float>(lin_acc ? partB_floats : 0);
-  sc.plan = plan;
-  sc.sel = need_sel ? sel_ws : out->sel;
-  sc.s_mean = need_sm ? sm_ws : out->s_mean;
+  Scratch sc = carve_estep(c->scratch.p, L, a, out);
 
-  uint8_t* flagged = out ? out->flagged : nullptr;
-  float* logL = out ? out->logL : nullptr;
-  uint32_t* top_mask = out ? out->top_mask : nullptr;
-  float* top_q = out ? out->top_q : nullptr;
-
-  const int Dp2 = Dp;
-  e = timed(c, "prep", s, [&] {
-    hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
-                                      sc.redo_count, s, sc.defer_count);
-    return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp2, p, s) : e2;
-  });
-  float* Aacc = a->accumulate ? acc->A : nullptr;
-  int tree_blocks = 0;
-  float* Bacc = a->accumulate ? acc->B : nullptr;
   if (a->accumulate) c->factor_ready = false;
   const bool factor_b = (a->flags & PROSPER_FLAG_FACTOR_B) != 0u;
   if (factor_b) {
@@ -594,8 +683,8 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
     if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "M-step workspace allocation failed");
   }
   // after B is complete: fork its factorisation onto the side stream
-  auto after_B = [&](hipStream_t st) -> hipError_t {
-    hipError_t e2 = hipEventRecord(c->ev_b, st);
+  auto after_B = [&](hipStream_t st2) -> hipError_t {
+    hipError_t e2 = hipEventRecord(c->ev_b, st2);
     if (e2 == hipSuccess) e2 = hipStreamWaitEvent(c->side, c->ev_b, 0);
     if (e2 == hipSuccess)
       e2 = timed(c, "mstep_factor", c->side,
@@ -603,25 +692,8 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
     if (e2 == hipSuccess) e2 = hipEventRecord(c->ev_f, c->side);
     return e2;
   };
-  double* scal = a->accumulate ? acc->scal : nullptr;
-  if (e == hipSuccess)
-    e = timed(c, "project_select", s, [&] {
-      return launch_project_select(model, prec, Y, N, D, Dp2, H, Hp, p, sc, flagged, scal, s);
-    });
-  if (e == hipSuccess)
-    e = timed(c, is_max_model(model) ? "states_max" : "states_lin", s, [&] {
-      if (is_max_model(model))
-        return launch_states_max(model, Hp, a->gamma, N, D, Dp2, H, ns, tab->act, Y, p, sc, logL,
-                                 top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
-      return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab->act, tab->sgn, p, sc, logL,
-                               top_mask, top_q, a->topk, Aacc != nullptr, Bacc, scal, c->num_cu,
-                               &tree_blocks, s);
-    });
-  if (e == hipSuccess && Aacc && !is_max_model(model))
-    e = timed(c, "stats", s, [&] {
-      return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s,
-                          factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 32 : 0);
-    });
+  e = enqueue_estep(c, a, Y, W, out, acc, s, p, sc, tab->act, tab->sgn, ns, c->num_cu,
+                    factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 32 : 0);
   if (e == hipSuccess && factor_b) e = hipStreamWaitEvent(s, c->ev_f, 0);
   if (e != hipSuccess) return hip_fail(c, e, "E-step launch");
   if (factor_b) {

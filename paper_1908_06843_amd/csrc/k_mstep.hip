@@ -17,16 +17,17 @@
 // workspace header and leaves W unchanged.
 //   k_ms_panel : right-looking blocked Cholesky B = L L^T with 64-column
 //                panels.  Every workgroup factors the 64 x 64 diagonal block
-//                in one wave's registers (lane i holds row i), then solves 256
-//                of the rows below it.  The factor is written twice: L in the
-//                lower triangle and L^T in the upper one, so that both
-//                triangular solves read contiguous rows;
+//                in one wave's registers (lane i holds row i) and inverts it
+//                (lane j forms column j of L_kk^-1), then forms 256 of the
+//                rows below as products with L_kk^-T.  L is written to the
+//                lower triangle and mirrored into the upper one, and the
+//                block inverses are kept (row-major and transposed), so that
+//                both substitutions of the solve read coalesced rows;
 //   k_ms_syrk  : trailing update T -= P P^T on 32 x 32 tiles;
-//   k_ms_solve : one wave per pixel d: forward and backward substitution of
-//                x with its 64-row blocks in registers (lane i holds x[64 m + i]);
-//                the 64 x 64 blocks of L are staged in LDS one step ahead,
-//                shared by the workgroup's four pixels; then W_new row d and
-//                its share of tr(W_new^T A).
+//   k_ms_solve : one wave per pixel d: block forward and backward
+//                substitution of x, each block step a few matrix-vector
+//                products (the diagonal ones with the stored inverses);
+//                then W_new row d and its share of tr(W_new^T A).
 // MCA: W_new = A / B elementwise where B > 0 (hard-max responsibilities),
 // pi as above, sigma^2 = sum <||y - f(s)||^2> / (N D).
 #include "dev_common.hpp"
@@ -42,13 +43,17 @@ struct MstepHdr {
   int pad;
 };
 
-// Workspace: header | M (H x H) | invd (H) | trp (D), each 256-byte aligned.
+// Workspace: header | M (H x H) | Dinv | DinvT (64 x 64 per diagonal block) |
+// trp (D), each 256-byte aligned.
 struct MstepWork {
   MstepHdr* hdr;
   double* M;
-  double* invd;
+  double* Dinv;
+  double* DinvT;
   double* trp;
 };
+
+static size_t dinv_bytes(int H) { return round_up((size_t)((H + NB - 1) / NB) * NB * NB * 8, 256); }
 
 static MstepWork carve_mstep(void* work, int D, int H) {
   char* p = reinterpret_cast<char*>(work);
@@ -57,8 +62,10 @@ static MstepWork carve_mstep(void* work, int D, int H) {
   p += 256;
   w.M = reinterpret_cast<double*>(p);
   p += round_up((size_t)H * H * 8, 256);
-  w.invd = reinterpret_cast<double*>(p);
-  p += round_up((size_t)H * 8, 256);
+  w.Dinv = reinterpret_cast<double*>(p);
+  p += dinv_bytes(H);
+  w.DinvT = reinterpret_cast<double*>(p);
+  p += dinv_bytes(H);
   w.trp = reinterpret_cast<double*>(p);
   return w;
 }
@@ -134,15 +141,21 @@ __device__ __forceinline__ void factor_rows(double (&a)[NBK], int lane, double* 
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Panel at kb (nb = min(64, H - kb) columns): factor the diagonal block,
-// then L[i, kb:kb+nb] = M[i, kb:kb+nb] L_kk^-T for the 256 rows of this
-// workgroup's share of i >= kb + nb.  Each workgroup factors the (small)
-// diagonal block itself; workgroup 0 writes it back with its mirror and
-// the inverse pivots.
+// Panel at kb (nb = min(64, H - kb) columns): factor the diagonal block
+// L_kk, invert it (column j of L_kk^-1 by forward substitution down the
+// rows, one lane per column), then form the rows below as
+// L[i, kb:kb+nb] = M[i, kb:kb+nb] L_kk^-T, a product with no dependent
+// chain.  Every workgroup factors the (small) diagonal block itself and
+// solves 256 of the rows below; workgroup 0 writes the block, its mirror,
+// L_kk^-1 (row-major and transposed) and nothing else.  Each row below is
+// written to the lower triangle and mirrored into the upper one, so that
+// both substitutions of the solve read coalesced rows.
 __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restrict__ M,
-                                                  double* __restrict__ invd,
+                                                  double* __restrict__ Dinv,
+                                                  double* __restrict__ DinvT,
                                                   MstepHdr* __restrict__ hdr) {
-  __shared__ double Ls[NB][NB + 1];  // transposed: Ls[c][r] = L[r][c]
+  __shared__ double Ls[NB][NB + 1];  // L_kk, row-major (lower)
+  __shared__ double Xs[NB][NB + 1];  // L_kk^-1, row-major (lower)
   __shared__ double inv_s[NB];
   __shared__ double colb[NB];
   const int nb = min(NB, H - kb);
@@ -162,23 +175,45 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     factor_rows<NB>(a, lane, colb, myinv, bad);
     static_for<0, NB>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
-      Ls[c][lane] = (c <= lane) ? a[c] : 0.0;
+      Ls[lane][c] = (c <= lane) ? a[c] : 0.0;
     });
     inv_s[lane] = myinv;
     if (blockIdx.x == 0 && bad && lane == 0) hdr->failed = 1;
   }
   __syncthreads();
+  if (tid < 64) {
+    // x[i] = (L_kk^-1)[i][lane]: (delta_i,lane - sum_{m<i} L[i][m] x[m]) / L[i][i]
+    double x[NB];
+    static_for<0, NB>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      __builtin_amdgcn_sched_barrier(0);
+      double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+      static_for<0, i>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        if constexpr ((m & 1) == 0) s0 = fma(-Ls[i][m], x[m], s0);
+        else s1 = fma(-Ls[i][m], x[m], s1);
+      });
+      x[i] = (s0 + s1) * inv_s[i];
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, NB>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      Xs[i][lane] = x[i];
+    });
+  }
+  __syncthreads();
   if (blockIdx.x == 0) {
-    // write the factored block and its mirror, and the inverse pivots
+    const int blk = kb / NB;
     for (int e = tid; e < NB * NB; e += 256) {
       const int r = e >> 6, c = e & 63;
       if (r < nb && c <= r) {
-        const double v = Ls[c][r];
+        const double v = Ls[r][c];
         M[(int64_t)(kb + r) * H + kb + c] = v;
         M[(int64_t)(kb + c) * H + kb + r] = v;
       }
+      Dinv[(int64_t)blk * NB * NB + e] = Xs[r][c];
+      DinvT[(int64_t)blk * NB * NB + e] = Xs[c][r];
     }
-    if (tid < nb) invd[kb + tid] = inv_s[tid];
   }
   // rows below the block exist only when the block is full (nb == 64)
   const int i = kb + nb + blockIdx.x * 256 + tid;
@@ -189,17 +224,18 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     constexpr int c = decltype(cc)::value;
     x[c] = xp[c];
   });
-  // right-looking: x_c /= L_cc, then x_c' -= x_c L_c'c for c' > c
-  static_for<0, NB>([&](auto cc) {
-    constexpr int c = decltype(cc)::value;
-    // one scheduling region per step: otherwise every LDS read of the block
-    // is hoisted to the top and the registers spill
+  // L[i][c] = sum_{m <= c} M[i][m] (L_kk^-1)[c][m], highest c first so that
+  // each result can replace its input (smaller c read only m <= c)
+  static_for<0, NB>([&](auto cr) {
+    constexpr int c = NB - 1 - decltype(cr)::value;
     __builtin_amdgcn_sched_barrier(0);
-    x[c] = x[c] * inv_s[c];
-    static_for<c + 1, NB>([&](auto c2c) {
-      constexpr int c2 = decltype(c2c)::value;
-      x[c2] = fma(-x[c], Ls[c][c2], x[c2]);
+    double s0 = 0.0, s1 = 0.0;
+    static_for<0, c + 1>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      if constexpr ((m & 1) == 0) s0 = fma(x[m], Xs[c][m], s0);
+      else s1 = fma(x[m], Xs[c][m], s1);
     });
+    x[c] = s0 + s1;
   });
   __builtin_amdgcn_sched_barrier(0);
   static_for<0, NB>([&](auto cc) {
@@ -258,141 +294,93 @@ __global__ __launch_bounds__(256) void k_ms_syrk(int H, int kb, double* __restri
   }
 }
 
-// Block steps of the two substitutions on 64-row blocks (compile-time list):
-// forward: for each block mb its diagonal solve, then its update of every
-// block below; backward: blocks in reverse, diagonal solve, then its update
-// of every block above.  Each step reads the 64 x 64 block of M in rows
-// 64 mb .. + 64 and columns 64 tgt .. + 64.
-struct SolveStep {
-  int mb, tgt, kind;  // kind: 0 forward diagonal, 1 forward update, 2 backward diagonal, 3 backward update
-};
-template <int MB>
-struct SolveSteps {
-  SolveStep s[MB * (MB + 1)];
-  constexpr SolveSteps() : s() {
-    int k = 0;
-    for (int mb = 0; mb < MB; ++mb) {
-      s[k++] = SolveStep{mb, mb, 0};
-      for (int m = mb + 1; m < MB; ++m) s[k++] = SolveStep{mb, m, 1};
-    }
-    for (int mb = MB - 1; mb >= 0; --mb) {
-      s[k++] = SolveStep{mb, mb, 2};
-      for (int m = 0; m < mb; ++m) s[k++] = SolveStep{mb, m, 3};
-    }
-  }
-};
-
-// x = B^-1 a_d for pixel d = 4 blockIdx.x + wave, H <= 64 MB.  Lane i holds
-// x[64 m + i] in x[m].  Uses M[p][q] = L[max(p,q)][min(p,q)]: row kb + c of
-// M holds column kb + c of L to the right of the diagonal and row kb + c of
-// L to its left.  The M block of each step is staged in LDS by the whole
-// workgroup (shared by its four pixels) one step ahead of its use.  Writes
-// row d of W_new and the wave's part of tr(W_new^T A).
-template <int MB>
+// x = B^-1 a_d for pixel d = 4 blockIdx.x + wave (one wave per pixel), with
+// the factor B = L L^T and the inverses of its 64 x 64 diagonal blocks:
+//   forward   y_b = L_bb^-1 (a_b - sum_{k<b} L_bk y_k)
+//   backward  x_b = L_bb^-T (y_b - sum_{k>b} L_kb^T x_k)
+// Lane l owns row 64 b + l of each block step; the vector lives in LDS and is
+// read by broadcast.  L_bk (k < b) is read from its mirror in the upper
+// triangle and L_kb^T (k > b) from the lower one, so every matrix read of a
+// wave is one coalesced 512-byte row.  There is no scalar dependent chain:
+// each block step is a few matrix-vector products.  Writes row d of W_new and
+// the wave's part of tr(W_new^T A).
 __global__ __launch_bounds__(256) void k_ms_solve(int D, int H, const float* __restrict__ A,
                                                   const float* __restrict__ Bup,
                                                   const double* __restrict__ M,
-                                                  const double* __restrict__ invd,
+                                                  const double* __restrict__ Dinv,
+                                                  const double* __restrict__ DinvT,
                                                   const MstepHdr* __restrict__ hdr,
                                                   const float* W_old, float* W_new,
                                                   double* __restrict__ trp) {
-  constexpr SolveSteps<MB> steps{};
-  constexpr int NS = MB * (MB + 1);
-  __shared__ double Ms[2][64][64];
-  __shared__ double Is[2][64];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int d = blockIdx.x * 4 + (tid >> 6);
+  extern __shared__ double xs_all[];  // [4][Hpad + 64]: the vector, then a 64-entry buffer
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Hpad = round_up(H, NB), nblk = Hpad / NB;
+  double* x = xs_all + (size_t)wave * (Hpad + NB);
+  double* t = x + Hpad;
+  const int d = blockIdx.x * 4 + wave;
   const bool dok = d < D;
   const int64_t row = (int64_t)(dok ? d : 0) * H;
   const bool failed = hdr->failed != 0;
-  double x[MB];
-  bool act[MB];
-  static_for<0, MB>([&](auto mc) {
-    constexpr int m = decltype(mc)::value;
-    const int h = 64 * m + lane;
-    act[m] = h < H && Bup[(int64_t)(h < H ? h : 0) * H + (h < H ? h : 0)] > 0.0f;
-    const float a = A[row + (h < H ? h : 0)];
-    x[m] = act[m] ? (double)a : 0.0;
-  });
-  // staged block of a step: element (c, i) = M[kb + c][64 tgt + i] (zero
-  // outside H).  Diagonal blocks are staged pre-multiplied by the inverse
-  // pivot of row c and with the already-final side of the triangle zeroed,
-  // so the substitution is one fma per column and every lane scales its own
-  // value at the end.  Global loads run two steps ahead (two register sets),
-  // the LDS copy one step ahead (two buffers).
-  double reg[2][16];
-  double ireg[2] = {0.0, 0.0};
-  auto load_block = [&](int set, int mb, int tgt, int kind) {
-    const int kb = 64 * mb, cb = 64 * tgt;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = tid + 256 * u, c = e >> 6, i = e & 63;
-      bool ok = kb + c < H && cb + i < H;
-      if (kind == 0) ok = ok && i > c;
-      if (kind == 2) ok = ok && i < c;
-      const double v = M[(int64_t)(ok ? kb + c : 0) * H + (ok ? cb + i : 0)];
-      double sc = 1.0;
-      if (kind == 0 || kind == 2) sc = invd[kb + c < H ? kb + c : 0];
-      reg[set][u] = ok ? v * sc : 0.0;
-    }
-    if (tid < 64) {
-      const double v = invd[kb + tid < H ? kb + tid : 0];
-      ireg[set] = kb + tid < H ? v : 0.0;
-    }
-  };
-  auto store_block = [&](int set, int buf) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = tid + 256 * u;
-      Ms[buf][e >> 6][e & 63] = reg[set][u];
-    }
-    if (tid < 64) Is[buf][tid] = ireg[set];
-  };
-  auto step_live = [&](const SolveStep& st) { return 64 * st.mb < H && 64 * st.tgt < H; };
-  load_block(0, steps.s[0].mb, steps.s[0].tgt, steps.s[0].kind);
-  // loads are unconditional (clamped addresses) so that the waits before the
-  // LDS copies count only the older loads
-  if constexpr (NS > 1) load_block(1, steps.s[1].mb, steps.s[1].tgt, steps.s[1].kind);
-  store_block(0, 0);
+  for (int h = lane; h < Hpad; h += 64) {
+    const int hc = h < H ? h : 0;
+    const bool act = h < H && Bup[(int64_t)hc * H + hc] > 0.0f;
+    const float a = A[row + hc];
+    x[h] = act ? (double)a : 0.0;
+  }
   __syncthreads();
-  static_for<0, NS>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    constexpr SolveStep st = steps.s[k];
-    constexpr int buf = k & 1;
-    const int kb = 64 * st.mb;
-    if constexpr (k + 2 < NS) {
-      constexpr SolveStep n2 = steps.s[k + 2];
-      load_block(k & 1, n2.mb, n2.tgt, n2.kind);
-    }
-    if (step_live(st)) {
-      const int nb = min(64, H - kb);
-      if constexpr (st.kind == 0) {
-        // v_i -= (L_ic / L_cc) v_c for i > c; then x_i = v_i / L_ii
-#pragma unroll 16
-        for (int c = 0; c < nb; ++c)
-          x[st.mb] = fma(-Ms[buf][c][lane], readlane_d(x[st.mb], c), x[st.mb]);
-        x[st.mb] *= Is[buf][lane];
-      } else if constexpr (st.kind == 2) {
-#pragma unroll 16
-        for (int c = nb - 1; c >= 0; --c)
-          x[st.mb] = fma(-Ms[buf][c][lane], readlane_d(x[st.mb], c), x[st.mb]);
-        x[st.mb] *= Is[buf][lane];
-      } else {
-        double a0 = 0.0, a1 = 0.0;
+  // forward
+  for (int b = 0; b < nblk; ++b) {
+    const int r = NB * b + lane;
+    const int rc = r < H ? r : H - 1;
+    double s0 = x[r], s1 = 0.0;
+    for (int k = 0; k < b; ++k) {
+      const double* Mk = M + (int64_t)NB * k * H + rc;  // M[64k + m][r] = L[r][64k + m]
 #pragma unroll 8
-        for (int c = 0; c + 1 < nb; c += 2) {
-          a0 = fma(Ms[buf][c][lane], readlane_d(x[st.mb], c), a0);
-          a1 = fma(Ms[buf][c + 1][lane], readlane_d(x[st.mb], c + 1), a1);
-        }
-        if (nb & 1) a0 = fma(Ms[buf][nb - 1][lane], readlane_d(x[st.mb], nb - 1), a0);
-        x[st.tgt] -= a0 + a1;
+      for (int m = 0; m < NB; m += 2) {
+        s0 = fma(-Mk[(int64_t)m * H], x[NB * k + m], s0);
+        s1 = fma(-Mk[(int64_t)(m + 1) * H], x[NB * k + m + 1], s1);
       }
     }
-    if constexpr (k + 1 < NS) {
-      store_block((k + 1) & 1, buf ^ 1);
-      __syncthreads();
+    t[lane] = r < H ? s0 + s1 : 0.0;
+    __syncthreads();
+    const double* Dt = DinvT + (int64_t)b * NB * NB + lane;  // DinvT[m][l] = Linv[l][m]
+    double y0 = 0.0, y1 = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < NB; m += 2) {
+      y0 = fma(Dt[m * NB], t[m], y0);
+      y1 = fma(Dt[(m + 1) * NB], t[m + 1], y1);
     }
-  });
+    x[r] = y0 + y1;
+    __syncthreads();
+  }
+  // backward
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int r = NB * b + lane;
+    const int rc = r < H ? r : H - 1;
+    double s0 = x[r], s1 = 0.0;
+    for (int k = b + 1; k < nblk; ++k) {
+      const int kmax = min(NB, H - NB * k);
+      const double* Mk = M + (int64_t)NB * k * H + rc;  // M[64k + m][r] = L[64k + m][r]
+      int m = 0;
+#pragma unroll 4
+      for (; m + 1 < kmax; m += 2) {
+        s0 = fma(-Mk[(int64_t)m * H], x[NB * k + m], s0);
+        s1 = fma(-Mk[(int64_t)(m + 1) * H], x[NB * k + m + 1], s1);
+      }
+      if (m < kmax) s0 = fma(-Mk[(int64_t)m * H], x[NB * k + m], s0);
+    }
+    t[lane] = r < H ? s0 + s1 : 0.0;
+    __syncthreads();
+    const double* Dr = Dinv + (int64_t)b * NB * NB + lane;  // Dinv[m][l] = Linv[m][l]
+    double y0 = 0.0, y1 = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < NB; m += 2) {
+      y0 = fma(Dr[m * NB], t[m], y0);
+      y1 = fma(Dr[(m + 1) * NB], t[m + 1], y1);
+    }
+    x[r] = y0 + y1;
+    __syncthreads();
+  }
   if (!dok) return;
   if (failed) {
     for (int h = lane; h < H; h += 64) W_new[row + h] = W_old[row + h];
@@ -400,18 +388,15 @@ __global__ __launch_bounds__(256) void k_ms_solve(int D, int H, const float* __r
     return;
   }
   double tr = 0.0;
-  static_for<0, MB>([&](auto mc) {
-    constexpr int m = decltype(mc)::value;
-    const int h = 64 * m + lane;
-    if (h < H) {
-      if (act[m]) {
-        tr = fma(x[m], (double)A[row + h], tr);
-        W_new[row + h] = (float)x[m];
-      } else {
-        W_new[row + h] = W_old[row + h];
-      }
+  for (int h = lane; h < H; h += 64) {
+    const bool act = Bup[(int64_t)h * H + h] > 0.0f;
+    if (act) {
+      tr = fma(x[h], (double)A[row + h], tr);
+      W_new[row + h] = (float)x[h];
+    } else {
+      W_new[row + h] = W_old[row + h];
     }
-  });
+  }
   tr = wave_sum_d(tr);
   if (lane == 0) trp[d] = tr;
 }
@@ -455,15 +440,7 @@ __global__ void k_mstep_scalars_mca(int D, int H, const double* __restrict__ sca
 
 size_t mstep_workspace_bytes(int model, int D, int H) {
   if (is_max_model(model)) return 256;
-  return 256 + round_up((size_t)H * H * 8, 256) + round_up((size_t)H * 8, 256) +
-         round_up((size_t)D * 8, 256);
-}
-
-template <int MB>
-static void launch_solve(int D, int H, const float* A, const float* B, const MstepWork& w,
-                         const float* W_old, float* W_new, hipStream_t st) {
-  hipLaunchKernelGGL(k_ms_solve<MB>, dim3((unsigned)((D + 3) / 4)), dim3(256), 0, st, D, H, A, B,
-                     w.M, w.invd, w.hdr, W_old, W_new, w.trp);
+  return 256 + round_up((size_t)H * H * 8, 256) + 2 * dinv_bytes(H) + round_up((size_t)D * 8, 256);
 }
 
 hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* work,
@@ -483,7 +460,8 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
     const int nb = (H - kb < NB) ? H - kb : NB;
     const int below = H - kb - nb;
     const unsigned nblk = below > 0 ? (unsigned)((below + 255) / 256) : 1u;
-    hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.invd, w.hdr);
+    hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.Dinv, w.DinvT,
+                       w.hdr);
     if (below > 0) {
       const int nt = (below + 31) / 32;
       hipLaunchKernelGGL(k_ms_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, H, kb,
@@ -505,11 +483,11 @@ hipError_t launch_mstep_solve(int model, int D, int H, const float* A, const flo
   }
   if (H > 16 * 64) return hipErrorInvalidValue;
   const MstepWork w = carve_mstep(work, D, H);
-  if (H <= 64) launch_solve<1>(D, H, A, B, w, W_old, W_new, st);
-  else if (H <= 128) launch_solve<2>(D, H, A, B, w, W_old, W_new, st);
-  else if (H <= 256) launch_solve<4>(D, H, A, B, w, W_old, W_new, st);
-  else if (H <= 512) launch_solve<8>(D, H, A, B, w, W_old, W_new, st);
-  else launch_solve<16>(D, H, A, B, w, W_old, W_new, st);
+  const size_t lds = (size_t)4 * (round_up(H, NB) + NB) * 8;
+  hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(k_ms_solve), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ms_solve, dim3((unsigned)((D + 3) / 4)), dim3(256), lds, st, D, H, A, B,
+                     w.M, w.Dinv, w.DinvT, w.hdr, W_old, W_new, w.trp);
   hipLaunchKernelGGL(k_ms_scalars_lin, dim3(1), dim3(256), 0, st, D, H, scal, w.trp, theta_new);
   return hipGetLastError();
 }

@@ -114,6 +114,16 @@ __global__ __launch_bounds__(256) void k_norms(const float* __restrict__ Pt32, i
   }
 }
 
+// wmax[d] = max_h W_dh (unclamped), one thread per pixel over its contiguous row.
+__global__ __launch_bounds__(256) void k_rowmax(const float* __restrict__ W, int D, int H,
+                                                float* __restrict__ wmax) {
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= D) return;
+  float m = -INFINITY;
+  for (int h = 0; h < H; ++h) m = fmaxf(m, W[(int64_t)d * H + h]);
+  wmax[d] = m;
+}
+
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
                        const Prepared& p, hipStream_t st) {
   const int relu = (model == PROSPER_MCA && H > 1) ? 1 : 0;
@@ -127,6 +137,8 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
   }
   hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi, p.hn_lo,
                      p.pnorm);
+  if (model == PROSPER_MCA)
+    hipLaunchKernelGGL(k_rowmax, dim3((D + 255) / 256), dim3(256), 0, st, W, D, H, p.wmax);
   return hipGetLastError();
 }
 

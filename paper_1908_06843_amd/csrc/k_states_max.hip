@@ -2,8 +2,11 @@
 //
 // f_d(s) = max_h s_h W_dh.  For a state with k < H active latents the
 // inactive ones contribute 0 to the max, so f_d = max(0, max_{j in s} P_dj)
-// with P = max(W, 0); the state with all H latents active (reachable only
-// when H' = H = gamma) takes the max over W itself.  The log-joint is taken
+// with P = max(W, 0), the rows the projection ranked.  The state with all H
+// latents active (reachable only when H' = H = gamma) has no inactive latent:
+// its superposition is max_h W_dh of the unclamped W, which is negative on a
+// pixel whose whole row of W is negative; the parameter preparation stores
+// that row maximum (wmax) and the walk takes it for this state.  The log-joint is taken
 // with the direct residual (log2 units, up to the constant c0):
 //   lj(s) = k(s) c1 - lam ||y - f(s)||^2                   (Eq. 1 + Eq. 2)
 // Unlike the linear models, the form relative to the zero state would carry
@@ -42,7 +45,7 @@ template <bool MAG>
 __global__ __launch_bounds__(64) void k_states_max(
     const float* __restrict__ Y, int64_t N, int D, int Dp, int H, int Hp, int64_t nstates,
     const uint32_t* __restrict__ tab_act, const float* __restrict__ Pt32,
-    const int32_t* __restrict__ sel, const float* __restrict__ yy, const Theta* __restrict__ th,
+    const float* __restrict__ wmax, const int32_t* __restrict__ sel, const float* __restrict__ yy, const Theta* __restrict__ th,
     float* __restrict__ s_mean, float* __restrict__ logL, uint32_t* __restrict__ top_mask,
     float* __restrict__ top_q, int topk, float* __restrict__ A_num, float* __restrict__ B_den,
     double* __restrict__ scal) {
@@ -87,8 +90,12 @@ __global__ __launch_bounds__(64) void k_states_max(
           for (int i = 0; i < MCA_ND; ++i) {
             const int d = lane + 64 * i;
             if (i < nd && d < D) {
-              float mu = (MAG || floor0) ? 0.0f : -INFINITY;
+              float mu = 0.0f;
               uint32_t rem = act;
+              if (!MAG && !floor0) {
+                mu = wmax[d];
+                rem = 0u;
+              }
               while (rem) {
                 const int j = __ffs(rem) - 1;
                 rem &= rem - 1u;
@@ -262,17 +269,12 @@ hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int
   if (N <= 0) return hipSuccess;
   const size_t lds = states_max_lds_bytes(Hp, D, nstates, A_num != nullptr);
   const bool mag = model == PROSPER_MMCA;
-  static size_t configured[2] = {0, 0};
   const auto kern = mag ? k_states_max<true> : k_states_max<false>;
-  if (lds > configured[mag]) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    configured[mag] = lds;
-  }
+  hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+  if (e0 != hipSuccess) return e0;
   int64_t blocks = N < 8192 ? N : 8192;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, st, Y, N, D, Dp, H, Hp,
-                     nstates, tab_act, p.Pt32, s.sel, s.yy, p.theta, s.s_mean, logL, top_mask,
+                     nstates, tab_act, p.Pt32, p.wmax, s.sel, s.yy, p.theta, s.s_mean, logL, top_mask,
                      top_q, topk, A_num, B_den, scal);
   return hipGetLastError();
 }

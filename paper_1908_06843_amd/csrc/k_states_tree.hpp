@@ -384,13 +384,8 @@ __global__ __launch_bounds__(512) void k_states_tree_acc(
     if (acc_blocks > 0) {                                                                        \
       auto kern = k_states_tree_acc<HPV, GMV, TSCV>;                                             \
       const size_t lds = (size_t)H * (H + 1) / 2 * 4;                                            \
-      static size_t configured = 0;                                                              \
-      if (lds > configured) {                                                                    \
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                  \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);\
-        if (e != hipSuccess) return e;                                                           \
-        configured = lds;                                                                        \
-      }                                                                                          \
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);              \
+      if (e != hipSuccess) return e;                                                             \
       hipLaunchKernelGGL(kern, dim3((unsigned)acc_blocks), dim3(512), lds, st, s.sel, s.bc,      \
                          s.yy, p.G, H, N, p.theta, s.s_mean, logL, partB, stride, scal,          \
                          s.redo_list, s.redo_count);                                             \

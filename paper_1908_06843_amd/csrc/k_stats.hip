@@ -149,6 +149,8 @@ __global__ __launch_bounds__(256, 1) void k_stats_A_mfma(
     Sl[e] = (bf16)0.0f;
   }
   for (int e = tid; e < AT_PTS * AT_YS; e += 256) Yf[e] = 0.0f;
+  // every wave's zero fill must land before any wave scatters its first tile
+  __syncthreads();
   f32x4 acc[4][16];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -453,13 +455,8 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
     int ngB = tree_blocks, nB = 1;
     if (s.ss) {
       const size_t ldsB = (size_t)BSLICE_MAX * 4;
-      static size_t configured = 0;
-      if (ldsB > configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_stats_B),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsB);
-        if (e != hipSuccess) return e;
-        configured = ldsB;
-      }
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(k_stats_B), ldsB);
+      if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_stats_B, dim3((unsigned)(pl.ngroups * pl.nB)), dim3(256), ldsB, st, N,
                          H, Hp, s.sel, s.ss, pl.nB, pl.ppg, s.partB);
       ngB = pl.ngroups;
@@ -501,14 +498,12 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
                        D, H, nwg, s.partA, A);
     return hipGetLastError();
   }
-  static size_t configured[2] = {0, 0};
   const int which = Hp <= 16 ? 0 : 1;
   const void* kern = which == 0 ? reinterpret_cast<const void*>(k_stats_A<16>)
                                 : reinterpret_cast<const void*>(k_stats_A<32>);
-  if (ldsA > configured[which]) {
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsA);
+  {
+    hipError_t e = ensure_dynamic_lds(kern, ldsA);
     if (e != hipSuccess) return e;
-    configured[which] = ldsA;
   }
   const dim3 g((unsigned)(pl.ngroups * pl.nA));
   if (which == 0)

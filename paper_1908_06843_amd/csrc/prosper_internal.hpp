@@ -44,6 +44,8 @@ struct Prepared {
   float* hn_hi;     // H        1/2 ||P_h||^2 as an FP32 head ...
   float* hn_lo;     // H        ... and tail (FP64-accumulated)
   float* pnorm;     // 1        max_h ||P_h||_2
+  float* wmax;      // Dp       max_h W_dh of the unclamped W (MCA: the superposition of
+                    //          the state with all H latents active)
   Theta* theta;     // 1
 };
 
@@ -165,6 +167,39 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
                              uint8_t* flagged, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, float* A, float* B, double* scal, int num_cu,
                              hipStream_t s);
+
+// Raise a kernel's dynamic-LDS limit to at least `bytes` (once per kernel and
+// size; safe to call from several host threads).
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
+
+// E-step launch sequence shared by the entry points (host.hip).
+// Checks of an E-step call (validate_args plus pointer requirements).
+prosper_status check_estep(const prosper_args* a, const float* Y, const float* W,
+                           const prosper_point_out* out, const prosper_acc* acc,
+                           std::string* msg, int64_t* ns);
+// Per-point workspace of one E-step call: which pieces it needs and its size.
+struct EstepLayout {
+  bool need_sel = false, need_sm = false, lin_acc = false, tree_acc = false;
+  int defer_cap = 0, Hpad = 0;
+  size_t npairs = 0, partB_floats = 0, bytes = 0;
+  StatsPlan plan;
+};
+// num_cu sizes the statistics partials (one per walk / statistics
+// workgroup); defer_cap is the length of the projection's deferral list.
+EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int num_cu,
+                       int defer_cap);
+Scratch carve_estep(void* base, const EstepLayout& L, const prosper_args* a,
+                    const prosper_point_out* out);
+// Parameter prep, projection + preselection, state walk and statistics of one
+// E-step on stream s.  c may be NULL (no profiling).  after_B runs once B is
+// complete; reserve_cu CUs are left free for work it forks.
+hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, const float* W,
+                         const prosper_point_out* out, const prosper_acc* acc, hipStream_t s,
+                         const Prepared& p, const Scratch& sc, const uint32_t* tab_act,
+                         const uint32_t* tab_sgn, int64_t ns, int num_cu,
+                         const StatsHook& after_B, int reserve_cu);
+// Records the text of a failure of a context-less call (prosper_last_error(NULL)).
+prosper_status set_error(prosper_status st, const std::string& msg);
 
 // Whether a compile-time specialised state walk exists for this shape.
 bool has_tree_kernel(int model, int Hp, int gamma);

@@ -154,3 +154,44 @@ def test_em_bars_trajectory_and_monotone_free_energy():
     assert th[0] == pytest.approx(pi_ref, rel=1e-3)
     assert th[1] == pytest.approx(s_ref, rel=1e-3)
     assert rel(Wd.cpu().numpy(), W_ref) < 1e-3
+
+
+@pytest.mark.parametrize("H,D,inactive", [(320, 96, (5, 130, 319)), (64, 40, ()), (200, 256, (0, 199))])
+def test_mstep_solve_many_panels(H, D, inactive):
+    """The blocked FP64 solve over several 64-column panels (ragged last
+    panel, inactive latents inside and at the ends) against the plain
+    definition W = A B^-1 on the active block (numpy's dense solve), and
+    sigma^2 = (sum||y||^2 - tr(W^T A)) / (N D), pi = sum<k> / (N H)."""
+    import torch
+    from paper_1908_06843_amd import api
+    g = np.random.default_rng(H + D)
+    S = (g.random((4 * H, H)) < 0.1).astype(np.float64)
+    S += 0.05 * g.random(S.shape)
+    S[:, list(inactive)] = 0.0
+    B = S.T @ S
+    A = g.standard_normal((D, H)) @ B * 0.3
+    A[:, list(inactive)] = 0.0
+    act = np.diag(B) > 0
+    W_old = g.standard_normal((D, H)).astype(np.float32)
+    N = 5000.0
+    scal = np.array([7.0 * N / 10, -1e5, 50.0 * N * D / 10, 0.0, N])
+    Wr = W_old.astype(np.float64).copy()
+    Bf = np.triu(B).astype(np.float32)
+    Bs = np.triu(Bf).astype(np.float64)
+    Bs = Bs + np.triu(Bs, 1).T
+    Af = A.astype(np.float32).astype(np.float64)
+    Wr[:, act] = np.linalg.solve(Bs[np.ix_(act, act)], Af[:, act].T).T
+    s2 = (scal[2] - float((Wr[:, act] * Af[:, act]).sum())) / (N * D)
+    dev = torch.device("cuda", 0)
+    acc = {"A": torch.tensor(A, dtype=torch.float32, device=dev),
+           "B": torch.tensor(Bf, device=dev),
+           "scal": torch.tensor(scal, dtype=torch.float64, device=dev)}
+    Wn, th = api.mstep(acc, torch.tensor(W_old, device=dev), model="bsc")
+    torch.cuda.synchronize()
+    Wn, th = Wn.cpu().numpy(), th.cpu().numpy()
+    print(f"[mstep] H={H} D={D}: W {rel(Wn, Wr):.2e}", flush=True)
+    assert rel(Wn, Wr) < 1e-5
+    for h in inactive:
+        np.testing.assert_array_equal(Wn[:, h], W_old[:, h])
+    assert th[0] == pytest.approx(scal[0] / (N * H), rel=1e-12)
+    assert th[1] == pytest.approx(np.sqrt(s2), rel=1e-6)
