@@ -191,6 +191,31 @@ prosper_status prosper_estep(prosper_ctx* ctx, const prosper_args* args,
                              const prosper_point_out* out, const prosper_acc* acc,
                              void* stream);
 
+/* E-step without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory: code recorded into a HIP
+ * graph, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, outputs and errors as prosper_estep (accumulation and topk
+ * included), on the current HIP device, with no context: every intermediate
+ * (state table, parameter preparation, per-point workspace, statistics
+ * partials) lives in one file-scope device array of 64 MiB per GPU, held from
+ * library load until the process ends.  The call allocates and frees
+ * nothing; inputs and outputs are still the caller's.
+ *  - Returns EINVAL when the call's intermediates do not fit in 64 MiB (at
+ *    D = H = 256 and H' = 12 about 56 bytes per point plus 1 MB, and 13 MB
+ *    more with statistics, when sel and s_mean are supplied: N up to about
+ *    1.1 million, or 0.9 million with statistics), and for
+ *    PROSPER_FLAG_FACTOR_B (it needs a context's second stream).
+ *  - The array is shared by every call on that GPU and keeps the last call's
+ *    contents; each call clears what it needs cleared with kernels (no
+ *    memset).  Calls that overlap on one GPU (different streams or host
+ *    threads) race on it and must be serialised by the caller.
+ *  - Per-point outputs are bit-identical to prosper_estep's; the statistics
+ *    are summed over fewer partials (at most 32), so A, B and scal agree with
+ *    prosper_estep's up to FP32 summation order. */
+prosper_status prosper_estep_static(const prosper_args* args, const float* Y, const float* W,
+                                    const prosper_point_out* out, const prosper_acc* acc,
+                                    void* stream);
+
 /* M-step ----------------------------------------------------------------- */
 
 /* New parameters from one E-step's statistics, in FP64 on the device.

@@ -53,6 +53,7 @@ EXPORTS = [
     "prosper_validate_args", "prosper_state_count", "prosper_state_table",
     "prosper_estep", "prosper_mstep", "prosper_serve", "prosper_serve_submit",
     "prosper_serve_wait", "prosper_serve_stop", "prosper_profile", "prosper_profile_read",
+    "prosper_estep_static",
 ]
 
 _lib: Optional[C.CDLL] = None
@@ -83,6 +84,9 @@ def load() -> C.CDLL:
     lib.prosper_estep.argtypes = [vp, C.POINTER(Args), vp, vp, C.POINTER(PointOut),
                                   C.POINTER(Acc), vp]
     lib.prosper_estep.restype = i32
+    lib.prosper_estep_static.argtypes = [C.POINTER(Args), vp, vp, C.POINTER(PointOut),
+                                         C.POINTER(Acc), vp]
+    lib.prosper_estep_static.restype = i32
     lib.prosper_mstep.argtypes = [vp, C.POINTER(Args), C.POINTER(Acc), vp, vp, vp, vp]
     lib.prosper_mstep.restype = i32
     lib.prosper_serve.argtypes = [vp, vp, i32, i32, i32, i32, dbl, dbl, i32, sz, i32, i32, i32,

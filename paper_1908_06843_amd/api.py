@@ -97,7 +97,7 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
           want: Sequence[str] = ("sel", "s_mean", "logL", "flagged"),
           out: Optional[Dict[str, torch.Tensor]] = None,
           ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None,
-          factor_b: bool = False) -> Dict[str, torch.Tensor]:
+          factor_b: bool = False, static: bool = False) -> Dict[str, torch.Tensor]:
     """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
 
     Returns the requested per-point outputs: sel (N x H' int32), s_mean
@@ -107,6 +107,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     `factor_b` (with `acc`, BSC/TSC): this call completes the accumulation;
     B is factored for the next `mstep` with the same acc, overlapped with the
     A statistics (PROSPER_FLAG_FACTOR_B).
+    `static` calls prosper_estep_static, which allocates nothing (its
+    intermediates live in the library's fixed device array); no context.
     """
     _dev_f32("Y", Y)
     _dev_f32("W", W)
@@ -114,7 +116,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     D2, H = W.shape
     if D2 != D:
         raise ValueError("Y is N x D and W must be D x H")
-    ctx = ctx or context(Y.device.index)
+    if not static:
+        ctx = ctx or context(Y.device.index)
     dev = Y.device
     res: Dict[str, torch.Tensor] = {}
     out = dict(out or {})
@@ -149,6 +152,12 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
                           _lib.FLAG_FACTOR_B if factor_b else 0)
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lib = _lib.load()
+    if static:
+        with torch.cuda.device(dev):
+            _lib.check(lib.prosper_estep_static(C.byref(args), _ptr(Y), _ptr(W), C.byref(po),
+                                                C.byref(accs) if accs is not None else None,
+                                                C.c_void_p(st)))
+        return res
     _lib.check(lib.prosper_estep(ctx.handle, C.byref(args), _ptr(Y), _ptr(W), C.byref(po),
                                  C.byref(accs) if accs is not None else None, C.c_void_p(st)),
                ctx.handle)
