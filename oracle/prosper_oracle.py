@@ -25,6 +25,11 @@ Table 1; truncated posteriors per the same section and the introduction):
   renormalised on K_n.
 * M-step: the joint maximiser of sum_n sum_s q_n(s) log p(y_n, s | Theta).
 
+Annealing: an optional posterior temperature beta (q proportional to
+p(y, s)^beta on K_n), the deterministic annealing of the approximate
+posterior named for the schedule object of the user-interface section;
+logL is reported untempered.
+
 Readings where the paper is silent (each listed in the design notes):
   selection score = singleton log-joint, ties to the lower index, points
   flagged when the H'-th and (H'+1)-th scores lie within 1e-6 relative;
@@ -184,13 +189,20 @@ def preselect(r: np.ndarray, Hp: int, tie_rel: float = TIE_REL) -> Tuple[np.ndar
 # E-step
 # --------------------------------------------------------------------------
 def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
-                Hp: int, gamma: int, topk: int = 0, tab=None, sel=None) -> Dict:
+                Hp: int, gamma: int, topk: int = 0, tab=None, sel=None,
+                beta: float = 1.0) -> Dict:
     """Truncated posterior of one data point (all float64).
 
     `sel` (optional, H' distinct latents) replaces the preselected set I_n;
     it is meant for near-tie points, where more than one candidate set is a
     correct preselection and the posterior on another valid one is wanted.
-    The scores and the near-tie flag are still those of the data point."""
+    The scores and the near-tie flag are still those of the data point.
+
+    `beta` in (0, 1] is the posterior temperature of deterministic annealing
+    (the schedule object of the user-interface section anneals the
+    approximate posterior): q(s) is proportional to p(y, s | Theta)^beta on
+    K_n, and every moment and statistic is taken under that q.  logL stays
+    the untempered log sum_{s in K_n} p(y, s | Theta)."""
     y = np.asarray(y, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     H = W.shape[1]
@@ -207,7 +219,7 @@ def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: floa
     S = _embed(tab, sel, H)                      # |K| x H
     lj = log_joint(model, y, W, pi, sigma, S)    # |K|
     logL = float(logsumexp(lj))
-    q = np.exp(lj - logL)
+    q = np.exp(beta * lj - logsumexp(beta * lj))
     Ss = S[:, sel]                               # |K| x H' (values per slot)
     s_mean = q @ Ss
     ss_mean = (Ss * q[:, None]).T @ Ss
@@ -243,10 +255,10 @@ def estep_point(model: str, y: np.ndarray, W: np.ndarray, pi: float, sigma: floa
 
 def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
           Hp: int, gamma: int, topk: int = 0, keep_posterior: bool = False,
-          sel: np.ndarray = None) -> Dict:
+          sel: np.ndarray = None, beta: float = 1.0) -> Dict:
     """Truncated E-step over all points, plus the M-step accumulators.
-    `sel` (optional, N x H') replaces the preselection point by point (see
-    estep_point).
+    `sel` (optional, N x H') replaces the preselection point by point, and
+    `beta` is the posterior temperature (see estep_point).
 
     Returns per-point arrays (sel, flagged, logL, s_mean, ss_mean, k_mean,
     top_index, top_q) and the sums
@@ -274,7 +286,7 @@ def estep(model: str, Y: np.ndarray, W: np.ndarray, pi: float, sigma: float,
     post = []
     for n in range(N):
         p = estep_point(model, Y[n], W, pi, sigma, Hp, gamma, topk, tab,
-                        None if forced is None else forced[n])
+                        None if forced is None else forced[n], beta)
         sel[n], flagged[n], logL[n] = p["sel"], p["flagged"], p["logL"]
         s_mean[n], ss_mean[n], k_mean[n] = p["s_mean"], p["ss_mean"], p["k_mean"]
         if topk:

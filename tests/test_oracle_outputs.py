@@ -19,6 +19,7 @@ from repeated dictionary columns.
 CPU only.
 """
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -198,3 +199,57 @@ def test_forced_candidate_set_is_the_restricted_posterior():
     np.testing.assert_allclose(p["s_mean"], mean[[0, 2, 4]], rtol=1e-10, atol=1e-14)
     with pytest.raises(ValueError):
         O.estep_point("bsc", y, W, pi, sigma, Hp, gamma, sel=[1, 1, 2])
+
+
+# ---------------------------------------------------------------- annealing
+def tempered_params(model, pi, sigma, beta):
+    """p(y, s)^beta is, up to a constant, the joint of the same model with the
+    prior probabilities raised to beta and renormalised and the noise
+    variance divided by beta."""
+    if model == "tsc":
+        a, z = (pi / 2) ** beta, (1 - pi) ** beta
+        return 2 * a / (2 * a + z), sigma / np.sqrt(beta)
+    a, z = pi ** beta, (1 - pi) ** beta
+    return a / (a + z), sigma / np.sqrt(beta)
+
+
+@pytest.mark.parametrize("model", ["bsc", "tsc", "mca", "mmca"])
+@pytest.mark.parametrize("beta", [0.5, 0.2])
+def test_tempered_posterior_is_the_posterior_of_a_rescaled_model(model, beta):
+    g = np.random.default_rng(41)
+    D, H, Hp, gamma = 6, 7, 5, 3
+    W = g.standard_normal((D, H))
+    if model == "mca":
+        W = np.abs(W)
+    pi, sigma = 0.2, 0.8
+    pt, st = tempered_params(model, pi, sigma, beta)
+    for n in range(3):
+        y = g.standard_normal(D) * 1.3
+        a = O.estep_point(model, y, W, pi, sigma, Hp, gamma, beta=beta,
+                          sel=O.estep_point(model, y, W, pi, sigma, Hp, gamma)["sel"])
+        b = O.estep_point(model, y, W, pt, st, Hp, gamma, sel=a["sel"])
+        np.testing.assert_allclose(a["q"], b["q"], rtol=1e-10, atol=1e-15)
+        np.testing.assert_allclose(a["s_mean"], b["s_mean"], rtol=1e-10, atol=1e-15)
+        # logL stays the untempered one
+        c = O.estep_point(model, y, W, pi, sigma, Hp, gamma, sel=a["sel"])
+        assert a["logL"] == pytest.approx(c["logL"], rel=1e-14)
+
+
+def test_tempered_posterior_brute_force_and_the_flat_limit():
+    g = np.random.default_rng(43)
+    D, H, pi, sigma, beta = 5, 4, 0.3, 0.7, 0.35
+    W = g.standard_normal((D, H))
+    y = g.standard_normal(D)
+    states = [np.array(v, dtype=float) for v in itertools.product((0, 1), repeat=H)]
+    lj = np.array([loop_log_joint("bsc", y, W, pi, sigma, s) for s in states])
+    q = np.exp(beta * lj - logsumexp(beta * lj))
+    p = O.estep_point("bsc", y, W, pi, sigma, H, H, beta=beta)
+    np.testing.assert_allclose(p["s_mean"], q @ np.array(states), rtol=1e-10)
+    # beta -> 0: uniform over K, so <s_j> = #{states with slot j} / |K|
+    Hp, gamma = 6, 3
+    W = g.standard_normal((8, 9))
+    y = g.standard_normal(8)
+    p = O.estep_point("bsc", y, W, pi, sigma, Hp, gamma, beta=1e-12)
+    K = sum(math.comb(Hp, k) for k in range(gamma + 1))
+    per = sum(math.comb(Hp - 1, k - 1) for k in range(1, gamma + 1))
+    np.testing.assert_allclose(p["s_mean"], per / K, rtol=1e-9)
