@@ -102,7 +102,12 @@ typedef struct {
                                topk <= |K| */
     int32_t accumulate;     /* 1: add the M-step sufficient statistics into acc */
     uint32_t flags;         /* PROSPER_FLAG_NONE or PROSPER_FLAG_FACTOR_B */
-    int32_t reserved;
+    float   beta;           /* posterior temperature of deterministic annealing (the
+                               schedule object of the paper's user-interface section):
+                               q_n(s) proportional to p(y_n, s | Theta)^beta on K_n, in
+                               (0, 1]; 0 stands for 1 (no annealing).  Moments, top-k
+                               and statistics use the tempered q; logL stays
+                               untempered.  beta != 1 runs the table-driven state walk. */
 } prosper_args;
 
 /* Per-point outputs of the E-step; any pointer may be NULL to skip it.

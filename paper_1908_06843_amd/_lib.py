@@ -36,7 +36,7 @@ class Args(C.Structure):
                 ("D", C.c_int32), ("H", C.c_int32), ("Hprime", C.c_int32),
                 ("gamma", C.c_int32), ("pi", C.c_double), ("sigma", C.c_double),
                 ("theta_dev", C.c_void_p), ("topk", C.c_int32), ("accumulate", C.c_int32),
-                ("flags", C.c_uint32), ("reserved", C.c_int32)]
+                ("flags", C.c_uint32), ("beta", C.c_float)]
 
 
 class PointOut(C.Structure):
@@ -119,9 +119,9 @@ def check(status: int, ctx=None):
 
 def make_args(model: str, precision: str, N: int, D: int, H: int, Hprime: int, gamma: int,
               pi: float = 0.5, sigma: float = 1.0, theta_dev: Optional[int] = None,
-              topk: int = 0, accumulate: int = 0, flags: int = 0) -> Args:
+              topk: int = 0, accumulate: int = 0, flags: int = 0, beta: float = 1.0) -> Args:
     return Args(MODELS[model], PRECISIONS[precision], N, D, H, Hprime, gamma, float(pi),
-                float(sigma), theta_dev, topk, accumulate, flags, 0)
+                float(sigma), theta_dev, topk, accumulate, flags, float(beta))
 
 
 def state_count(model: str, Hprime: int, gamma: int) -> int:

@@ -97,7 +97,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
           want: Sequence[str] = ("sel", "s_mean", "logL", "flagged"),
           out: Optional[Dict[str, torch.Tensor]] = None,
           ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None,
-          factor_b: bool = False, static: bool = False) -> Dict[str, torch.Tensor]:
+          factor_b: bool = False, static: bool = False,
+          beta: float = 1.0) -> Dict[str, torch.Tensor]:
     """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
 
     Returns the requested per-point outputs: sel (N x H' int32), s_mean
@@ -109,6 +110,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     A statistics (PROSPER_FLAG_FACTOR_B).
     `static` calls prosper_estep_static, which allocates nothing (its
     intermediates live in the library's fixed device array); no context.
+    `beta` is the posterior temperature of deterministic annealing (q
+    proportional to p(y, s)^beta; logL untempered).
     """
     _dev_f32("Y", Y)
     _dev_f32("W", W)
@@ -149,7 +152,7 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
         accs = _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]))
     args = _lib.make_args(model, precision, N, D, H, Hprime, gamma, pi, sigma,
                           _ptr(theta), topk, 1 if acc is not None else 0,
-                          _lib.FLAG_FACTOR_B if factor_b else 0)
+                          _lib.FLAG_FACTOR_B if factor_b else 0, beta)
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lib = _lib.load()
     if static:

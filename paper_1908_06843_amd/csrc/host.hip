@@ -241,6 +241,10 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "accumulate must be 0 or 1";
     return PROSPER_EINVAL;
   }
+  if (!(a->beta == 0.0f || (a->beta > 0.0f && a->beta <= 1.0f))) {
+    *msg = "beta (posterior temperature) outside (0, 1]";
+    return PROSPER_EINVAL;
+  }
   if ((a->flags & ~PROSPER_FLAG_FACTOR_B) != 0u) {
     *msg = "unknown flag bits";
     return PROSPER_EINVAL;
@@ -433,7 +437,8 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
   L.lin_acc = a->accumulate && !is_max_model(a->model);
   L.npairs = (size_t)Hp * (Hp + 1) / 2;
   L.plan = stats_plan(N, D, H, num_cu);
-  L.tree_acc = L.lin_acc && a->topk == 0 && has_tree_kernel(a->model, Hp, a->gamma) &&
+  L.tree_acc = L.lin_acc && a->topk == 0 && args_beta(a) == 1.0f &&
+               has_tree_kernel(a->model, Hp, a->gamma) &&
                (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
   L.partB_floats = L.tree_acc ? (size_t)num_cu * stats_bslice_floats() : L.plan.partB_floats;
   size_t sb = 0;
@@ -499,7 +504,7 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
   int tree_blocks = 0;
   hipError_t e = timed(c, "prep", s, [&] {
     hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
-                                      sc.redo_count, s, sc.defer_count);
+                                      sc.redo_count, s, sc.defer_count, args_beta(a));
     return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp, p, s) : e2;
   });
   if (e == hipSuccess)
@@ -513,7 +518,7 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
       return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL,
                                top_mask, top_q, a->topk, Aacc != nullptr, Bacc, scal, num_cu,
-                               &tree_blocks, s);
+                               &tree_blocks, s, args_beta(a));
     });
   if (e == hipSuccess && Aacc && !is_max_model(model))
     e = timed(c, "stats", s, [&] {

@@ -17,7 +17,7 @@ namespace prosper {
 __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
                         const double* __restrict__ theta_dev, Theta* __restrict__ th,
                         float* __restrict__ pnorm, int32_t* __restrict__ redo_count,
-                        int32_t* __restrict__ defer_count) {
+                        int32_t* __restrict__ defer_count, float beta) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double pi = theta_dev ? theta_dev[0] : pi_h;
   double sigma = theta_dev ? theta_dev[1] : sigma_h;
@@ -32,6 +32,7 @@ __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
   double c1 = (model == PROSPER_TSC) ? log(pi / (2.0 * (1.0 - pi))) : log(pi / (1.0 - pi));
   t.c1_2 = (float)(c1 * LOG2E);
   t.ln2 = (float)0.6931471805599453;
+  t.beta = beta;
   *th = t;
   *pnorm = 0.0f;
   if (redo_count) *redo_count = 0;
@@ -146,9 +147,9 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
 // before k_norms on the same stream.
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
-                             hipStream_t st, int32_t* defer_count) {
+                             hipStream_t st, int32_t* defer_count, float beta) {
   hipLaunchKernelGGL(k_theta, dim3(1), dim3(64), 0, st, model, D, H, pi, sigma, theta_dev,
-                     p.theta, p.pnorm, redo_count, defer_count);
+                     p.theta, p.pnorm, redo_count, defer_count, beta);
   return hipGetLastError();
 }
 

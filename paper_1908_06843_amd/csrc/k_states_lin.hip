@@ -42,6 +42,9 @@ __global__ __launch_bounds__(256) void k_states_generic(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   GenLds& S = sh[wave];
   const float lam2 = th->lam2, c1 = th->c1_2;
+  // annealing: moments under 2^(beta (lj - m)), logL from the untempered sum
+  const float beta = th->beta;
+  const bool tempered = beta != 1.0f;
   const int64_t Ntot = N;  // leading dimension of ss_out
   double acc_k = 0.0, acc_l = 0.0;
   // list mode: only the points named in list[0 .. *list_count)
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256) void k_states_generic(
     }
     const float m = wave_max(mx);
     // pass 2: weights and moments
-    float z = 0.0f;
+    float z = 0.0f, z1 = 0.0f;
     if (live) {
       for (int64_t k = lane; k < nstates; k += 64) {
         const uint32_t act = tab_act[k];
@@ -137,8 +140,10 @@ __global__ __launch_bounds__(256) void k_states_generic(
             L += (ni != nj) ? -v : v;
           }
         }
-        const float e = fast_exp2(L - m);
+        const float e1 = fast_exp2(L - m);
+        const float e = tempered ? fast_exp2(beta * (L - m)) : e1;
         z += e;
+        z1 += e1;
         rem = act;
         while (rem) {
           const int j = __ffs(rem) - 1;
@@ -157,11 +162,12 @@ __global__ __launch_bounds__(256) void k_states_generic(
       }
     }
     const float Z = wave_sum(z);
+    const float Z1 = tempered ? wave_sum(z1) : Z;
     __syncthreads();
     if (live) {
       const float invZ = 1.0f / Z;
       const double lL = th->c0 - (double)th->lam * (double)yy[n] +
-                        0.6931471805599453 * ((double)m + (double)log2f(Z));
+                        0.6931471805599453 * ((double)m + (double)log2f(Z1));
       float kpart = 0.0f;
       for (int j = lane; j < Hp; j += 64) {
         const float k2 = TSC ? S.K2[j] : S.M[j];
@@ -218,7 +224,7 @@ __global__ __launch_bounds__(256) void k_states_generic(
           ti[PROSPER_MAX_TOPK - 1] = 0x7fffffff;
         }
         if (lane == 0) {
-          if (top_q) top_q[n * topk + t] = fast_exp2(v - m) * invZ;
+          if (top_q) top_q[n * topk + t] = fast_exp2((tempered ? beta : 1.0f) * (v - m)) * invZ;
           if (top_mask) {
             if (TSC) {
               top_mask[(n * topk + t) * 2 + 0] = tab_act[id];
@@ -267,11 +273,11 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
                              const Prepared& p, const Scratch& s, float* logL,
                              uint32_t* top_mask, float* top_q, int topk, bool acc,
                              float* acc_B, double* scal, int num_cu, int* tree_blocks,
-                             hipStream_t st) {
+                             hipStream_t st, float beta) {
   if (tree_blocks) *tree_blocks = 0;
   if (N <= 0) return hipSuccess;
   const bool tsc = (model == PROSPER_TSC);
-  if (topk == 0 && has_tree_kernel(model, Hp, gamma)) {
+  if (topk == 0 && beta == 1.0f && has_tree_kernel(model, Hp, gamma)) {
     // training: B partials inside the walk when B's packed triangle fits in LDS
     int nblk = 0;
     if (acc && (int64_t)H * (H + 1) / 2 <= stats_bslice_floats()) {

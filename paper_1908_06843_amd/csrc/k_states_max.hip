@@ -137,9 +137,16 @@ __global__ __launch_bounds__(64) void k_states_max(
     }
     __syncthreads();
     const float m = wave_max(mx);
-    float z = 0.0f;
-    for (int64_t k = lane; k < nstates; k += 64) z += __builtin_amdgcn_exp2f(ljs[k] - m);
+    // annealing: q from 2^(beta (lj - m)), logL from the untempered sum
+    const float beta = th->beta;
+    float z = 0.0f, z1 = 0.0f;
+    for (int64_t k = lane; k < nstates; k += 64) {
+      const float d = ljs[k] - m;
+      z1 += __builtin_amdgcn_exp2f(d);
+      z += beta == 1.0f ? __builtin_amdgcn_exp2f(d) : __builtin_amdgcn_exp2f(beta * d);
+    }
     const float Z = wave_sum(z);
+    const float Z1 = beta == 1.0f ? Z : wave_sum(z1);
     const float invZ = 1.0f / Z;
     // ---- top-k: repeated arg-max below the previous winner in (lj desc, index asc)
     {
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(64) void k_states_max(
           id = take ? i2 : id;
         }
         if (lane == 0) {
-          if (top_q) top_q[n * topk + t] = __builtin_amdgcn_exp2f(v - m) * invZ;
+          if (top_q) top_q[n * topk + t] = __builtin_amdgcn_exp2f(beta * (v - m)) * invZ;
           if (top_mask) top_mask[n * topk + t] = tab_act[id];
         }
         pv = v;
@@ -177,7 +184,7 @@ __global__ __launch_bounds__(64) void k_states_max(
     // ---- q, moments, expected residual
     float res = 0.0f;
     for (int64_t k = lane; k < nstates; k += 64) {
-      const float q = __builtin_amdgcn_exp2f(ljs[k] - m) * invZ;
+      const float q = __builtin_amdgcn_exp2f(beta * (ljs[k] - m)) * invZ;
       res += q * Rs[k];
       ljs[k] = q;
     }
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(64) void k_states_max(
       for (int i = 0; i < MCA_ND; ++i) yy_n += (double)yv[i] * (double)yv[i];
       for (int w = 32; w >= 1; w >>= 1) yy_n += __shfl_xor(yy_n, w, 64);
     }
-    const double lL = th->c0 + 0.6931471805599453 * ((double)m + (double)log2f(Z) -
+    const double lL = th->c0 + 0.6931471805599453 * ((double)m + (double)log2f(Z1) -
                                                      (double)lam2 * yy_n);
     if (lane == 0) {
       if (logL) logL[n] = (float)lL;

@@ -33,7 +33,11 @@ struct Theta {
   float lam2;    // lam * log2(e)
   float c1_2;    // c1 * log2(e)
   float ln2;     // log(2)
+  float beta;    // posterior temperature (1 = none)
 };
+
+// The posterior temperature of an argument block (0 stands for 1).
+inline float args_beta(const prosper_args* a) { return a->beta == 0.0f ? 1.0f : a->beta; }
 
 // Per-(model, W) derived data, rebuilt by k_prep for every E-step call.
 struct Prepared {
@@ -109,7 +113,7 @@ Prepared carve_prep(void* base, int Dp, int H, int prec);
 // Launchers (each returns the first HIP error it sees).
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
-                             hipStream_t st, int32_t* defer_count = nullptr);
+                             hipStream_t st, int32_t* defer_count = nullptr, float beta = 1.0f);
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
                        const Prepared& p, hipStream_t st);
 // Entries of the projection's deferral list for N points: enough for a
@@ -124,12 +128,13 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
 // of partials in *tree_blocks), or the walk writes pair-major <s s^T> into
 // s.ss for the statistics kernel (*tree_blocks = 0).  Points handed to the
 // exact kernel add their <s s^T> straight into acc_B with atomics.
+// beta != 1 (annealing) always takes the table-driven kernel.
 hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int64_t nstates,
                              const uint32_t* tab_act, const uint32_t* tab_sgn,
                              const Prepared& p, const Scratch& s, float* logL,
                              uint32_t* top_mask, float* top_q, int topk, bool acc,
                              float* acc_B, double* scal, int num_cu, int* tree_blocks,
-                             hipStream_t st);
+                             hipStream_t st, float beta = 1.0f);
 // Max-superposition models: MCA and MMCA share the walk, statistics and M-step.
 inline bool is_max_model(int m) { return m == PROSPER_MCA || m == PROSPER_MMCA; }
 // MCA/MMCA state walk (max / largest-magnitude superposition).
@@ -193,6 +198,7 @@ Scratch carve_estep(void* base, const EstepLayout& L, const prosper_args* a,
 // Parameter prep, projection + preselection, state walk and statistics of one
 // E-step on stream s.  c may be NULL (no profiling).  after_B runs once B is
 // complete; reserve_cu CUs are left free for work it forks.
+// num_cu: the CU count the statistics partials of the layout were planned for.
 hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, const float* W,
                          const prosper_point_out* out, const prosper_acc* acc, hipStream_t s,
                          const Prepared& p, const Scratch& sc, const uint32_t* tab_act,

@@ -43,7 +43,7 @@ def oracle_run(name, N, theta, Hp, gamma, topk=0, seed=None):
     return O.estep(wl.model, Y, W, pi, sigma, Hp, gamma, topk=topk)
 
 
-def gpu_estep(model, prec, Y, W, pi, sigma, Hp, gamma, topk=0, accumulate=False):
+def gpu_estep(model, prec, Y, W, pi, sigma, Hp, gamma, topk=0, accumulate=False, beta=1.0):
     import torch
     from paper_1908_06843_amd import api
     dev = torch.device("cuda", 0)
@@ -51,7 +51,7 @@ def gpu_estep(model, prec, Y, W, pi, sigma, Hp, gamma, topk=0, accumulate=False)
     Wd = torch.from_numpy(np.ascontiguousarray(W, dtype=np.float32)).to(dev)
     acc = api.new_acc(model, W.shape[0], W.shape[1]) if accumulate else None
     out = api.estep(Yd, Wd, pi, sigma, Hprime=Hp, gamma=gamma, model=model, precision=prec,
-                    topk=topk, acc=acc)
+                    topk=topk, acc=acc, beta=beta)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in out.items()}
     if acc is not None:

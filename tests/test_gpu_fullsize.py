@@ -175,3 +175,54 @@ def test_mca_all_active_state_with_negative_row(prec):
     assert_parity(out, r, prec, "mca all-active")
     assert rel(out["A"], r["A"]) < 3e-5 and rel(out["B"], r["B"]) < 3e-5
     assert out["scal"][3] == pytest.approx(r["scal"][3], rel=2e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_every_point_a_near_tie_overflows_the_deferral_list(prec):
+    """8000 points, all with an exact tie at the selection boundary: more
+    than the deferral list holds, so the rest take the exact selection inside
+    the projection workgroups."""
+    from oracle import prosper_oracle as O
+    g = np.random.default_rng(31)
+    D, H, Hp, N = 64, 32, 4, 8000
+    W = g.standard_normal((D, H))
+    W /= np.linalg.norm(W, axis=0)
+    W[:, 9] = W[:, 5]
+    Y = (3.0 * (W[:, 0] + W[:, 1] + W[:, 2]) + 1.2 * W[:, 5])[None, :] \
+        + 0.01 * g.standard_normal((N, D))
+    Y, W = Y.astype(np.float32), W.astype(np.float32)
+    out = gpu_estep("bsc", prec, Y, W, 0.1, 0.5, Hp, 2)
+    idx = np.sort(g.choice(N, 300, replace=False))
+    r = O.estep("bsc", Y[idx], W, 0.1, 0.5, Hp, 2)
+    assert r["flagged"].all()
+    assert np.all(out["flagged"] == 1)
+    assert np.all(out["sel"] == [0, 1, 2, 5])
+    np.testing.assert_array_equal(out["sel"][idx], r["sel"])
+    tol = TOL[prec]
+    es = np.abs(out["s_mean"][idx] - r["s_mean"]).max()
+    el = (np.abs(out["logL"][idx] - r["logL"]) / np.maximum(np.abs(r["logL"]), 1)).max()
+    assert es <= tol[0] and el <= tol[1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_wide_exact_tie_at_the_selection_boundary(prec):
+    """54 identical columns tie at the selection boundary: the exact
+    selection must keep the lowest tied indices and flag every point."""
+    from oracle import prosper_oracle as O
+    g = np.random.default_rng(37)
+    D, H, Hp, N = 48, 64, 12, 700
+    W = g.standard_normal((D, H))
+    W /= np.linalg.norm(W, axis=0)
+    W[:, 10:] = W[:, 10:11]
+    Y = (3.0 * (W[:, 0] + W[:, 1] + W[:, 2]) + 1.0 * W[:, 10])[None, :] \
+        + 0.01 * g.standard_normal((N, D))
+    Y, W = Y.astype(np.float32), W.astype(np.float32)
+    out = gpu_estep("bsc", prec, Y, W, 0.05, 0.5, Hp, 3)
+    r = O.estep("bsc", Y[:60], W, 0.05, 0.5, Hp, 3)
+    assert np.all(r["sel"] == [0, 1, 2] + list(range(10, 19)))
+    assert np.all(out["sel"] == [0, 1, 2] + list(range(10, 19)))
+    assert np.all(out["flagged"] == 1)
+    tol = TOL[prec]
+    es = np.abs(out["s_mean"][:60] - r["s_mean"]).max()
+    el = (np.abs(out["logL"][:60] - r["logL"]) / np.maximum(np.abs(r["logL"]), 1)).max()
+    assert es <= tol[0] and el <= tol[1]
