@@ -33,8 +33,9 @@ MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # FP32 lane-op slots/s, non-packed: 39.3 T
 
 
-def state_walk_ops(Hp: int, gamma: int) -> int:
-    """Algorithmic VALU op slots per point of the unrolled walk (BSC).
+def state_walk_ops(Hp: int, gamma: int, model: str = "bsc") -> int:
+    """Algorithmic VALU op slots per point of the unrolled walk (BSC; for TSC
+    every active slot tuple comes in 2^k sign patterns, each a state).
 
     Per non-zero state: its log-joint from the parent's (1 add), the weight
     2^(lj - m) (1 sub + 1 transcendental at quarter rate = 4 slots), the
@@ -44,7 +45,7 @@ def state_walk_ops(Hp: int, gamma: int) -> int:
     1 add + 1 max each."""
     ops = 0
     for k in range(1, gamma + 1):
-        c = math.comb(Hp, k)
+        c = math.comb(Hp, k) * (2 ** k if model == "tsc" else 1)
         ops += c * (1 + 1 + 4 + 1 + 1 + (k - 1))
         if k >= 2:
             ops += c
@@ -53,22 +54,47 @@ def state_walk_ops(Hp: int, gamma: int) -> int:
     return ops
 
 
-def cpu_oracle_baseline(Y, W, pi, sigma, Hp, gamma, target_s):
+CPU_SHARE = 16  # host CPU share of one GPU on the benchmark machines
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_workers() -> int:
+    """Worker processes for the oracle: the CPUs this process may run on,
+    capped at the host share of one GPU."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(CPU_SHARE, avail))
+
+
+def cpu_oracle_baseline(model, Y, W, pi, sigma, Hp, gamma, target_s, seed=11):
     """Time the FP64 oracle on a bounded sample with a process pool."""
     import concurrent.futures as cf
     import numpy as np
     from oracle import prosper_oracle as O
-    cores = min(16, os.cpu_count() or 1)
+    cores = cpu_workers()
     t0 = time.perf_counter()
-    O.estep("bsc", Y[:8], W, pi, sigma, Hp, gamma)
+    O.estep(model, Y[:8], W, pi, sigma, Hp, gamma)
     per_pt = (time.perf_counter() - t0) / 8
     n = int(max(cores * 8, min(Y.shape[0], target_s * cores / max(per_pt, 1e-6) / 1.5)))
     n = min(n, Y.shape[0])
-    idx = np.sort(np.random.default_rng(11).choice(Y.shape[0], n, replace=False))
+    idx = np.sort(np.random.default_rng(seed).choice(Y.shape[0], n, replace=False))
     chunks = np.array_split(idx, cores)
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=cores, initializer=_one_thread) as ex:
-        parts = list(ex.map(_oracle_chunk, [(Y[c], W, pi, sigma, Hp, gamma) for c in chunks]))
+        parts = list(ex.map(_oracle_chunk,
+                            [(model, Y[c], W, pi, sigma, Hp, gamma) for c in chunks]))
     wall = time.perf_counter() - t0
     ref = {k: np.concatenate([p[k] for p in parts]) for k in ("sel", "s_mean", "logL", "flagged")}
     return idx, ref, wall, cores
@@ -86,8 +112,8 @@ def _one_thread():
 
 def _oracle_chunk(a):
     from oracle import prosper_oracle as O
-    Yc, W, pi, sigma, Hp, gamma = a
-    r = O.estep("bsc", Yc, W, pi, sigma, Hp, gamma)
+    model, Yc, W, pi, sigma, Hp, gamma = a
+    r = O.estep(model, Yc, W, pi, sigma, Hp, gamma)
     return {k: r[k] for k in ("sel", "s_mean", "logL", "flagged")}
 
 
@@ -109,13 +135,14 @@ def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
     """Warm up, then time `steps` EM iterations; returns (ms/step, profile)."""
     Wd = W0.clone()
     theta = theta0.clone()
-    acc = api.new_acc("bsc", wl.D, wl.H)
+    acc = api.new_acc(wl.model, wl.D, wl.H)
+    factor_b = wl.model in ("bsc", "tsc")
 
     def step():
         api.zero_acc(acc)
-        api.estep(Yd, Wd, Hprime=wl.Hprime, gamma=wl.gamma, precision=prec, theta=theta,
-                  acc=acc, want=(), ctx=ctx, factor_b=True)
-        api.mstep(acc, Wd, model="bsc", W_new=Wd, theta_new=theta, ctx=ctx)
+        api.estep(Yd, Wd, Hprime=wl.Hprime, gamma=wl.gamma, model=wl.model, precision=prec,
+                  theta=theta, acc=acc, want=(), ctx=ctx, factor_b=factor_b)
+        api.mstep(acc, Wd, model=wl.model, W_new=Wd, theta_new=theta, ctx=ctx)
 
     for _ in range(warmup):
         step()
@@ -199,13 +226,72 @@ def serving_bench(np, api, n_req, prec):
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "patches_per_s": patches / load_s}
 
-    at = {f"{f}x": poisson(f) for f in (0.5, 0.8)}
+    at = {f"{f}x": poisson(f) for f in (0.5, 0.8, 0.95)}
     srv.stop()
     return {"requests": len(reqs), "patches": patches,
             "saturated_patches_per_s": patches / sat_s,
             "offered_load": "poisson at 0.8x saturated request rate",
             "p50_ms": at["0.8x"]["p50_ms"], "p99_ms": at["0.8x"]["p99_ms"],
             "patches_per_s": at["0.8x"]["patches_per_s"], "by_load": at}
+
+
+def max_walk_ops(D: int, Hp: int, gamma: int, stats: bool) -> int:
+    """Algorithmic VALU op slots per point of the max-superposition walk:
+    per state and pixel the max over its k actives (k slots) and the squared
+    residual (2); with statistics, per state and pixel the winning slot (k)
+    and the two responsibility sums (2)."""
+    ops = 0
+    for k in range(0, gamma + 1):
+        c = math.comb(Hp, k)
+        ops += c * D * (k + 2)
+        if stats:
+            ops += c * D * (k + 2)
+    return ops
+
+
+def side_workload(name, np, torch, api, ctx, steps, warmup, cpu_s, no_cpu):
+    """One EM iteration per step on another model family's workload: its
+    timing, the roofline of its dominant E-step kernel, its error against the
+    FP64 oracle and the oracle's own rate on a bounded sample."""
+    import synth
+    wl = synth.WORKLOADS[name]
+    Y, _, _, _ = synth.make_workload(name)
+    W0, pi0, s0 = synth.initial_params(wl, Y)
+    K = api.state_count(wl.model, wl.Hprime, wl.gamma)
+    dev = torch.device("cuda", 0)
+    Yd = torch.tensor(Y, device=dev)
+    W0d = torch.tensor(W0, device=dev)
+    theta0 = torch.tensor([pi0, s0], dtype=torch.float64, device=dev)
+    prec = "fp32" if wl.model in ("mca", "mmca") else "bf16"
+    ms, wall_ms, prof, _, _ = run_em_steps(api, torch, Yd, W0d, theta0, wl, prec, steps,
+                                           warmup, ctx)
+    N = Y.shape[0]
+    dom = max((k for k in prof if not k.startswith("mstep")), key=lambda k: prof[k]["ms"])
+    roof = roofline(dom, prof[dom]["ms"] / prof[dom]["launches"] * 1e-3, N, wl)
+    rec = {"workload": f"{wl.model.upper()} {name}: D={wl.D} H={wl.H} N={N} H'={wl.Hprime} "
+                       f"gamma={wl.gamma} |K|={K}, one EM iteration",
+           "metric": "truncated E-step joint evals/s", "value": N * K / (ms * 1e-3),
+           "unit": "joint evals/s", "ms_per_step": ms, "wall_ms_per_step": wall_ms,
+           "dtype": "bf16" if prec == "bf16" else "f32",
+           "kernel_us": {k: v["ms"] / v["launches"] * 1e3 for k, v in prof.items()},
+           "roofline": roof, "cpu_baseline": None, "error_vs_fp64_oracle": None}
+    if not no_cpu:
+        idx, ref, wall, cores = cpu_oracle_baseline(wl.model, Y, W0, pi0, s0, wl.Hprime,
+                                                    wl.gamma, cpu_s)
+        rec["cpu_baseline"] = {
+            "value": len(idx) * K / wall, "unit": "joint evals/s", "cores": cores,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{len(idx)} of {N} points (seeded), full E-step per point, "
+                      f"{wall:.1f} s wall on {cores} processes x 1 BLAS thread"}
+        out = api.estep(Yd, W0d, pi0, s0, Hprime=wl.Hprime, gamma=wl.gamma, model=wl.model,
+                        precision=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
+        rec["error_vs_fp64_oracle"] = error_stats(g, ref)
+    print(f"# {name}: {ms:.3f} ms/step  " +
+          "  ".join(f"{k} {v:.1f}us" for k, v in rec["kernel_us"].items()),
+          file=sys.stderr, flush=True)
+    return rec
 
 
 def project_select_work(N, D, H, Hp):
@@ -229,7 +315,11 @@ def roofline(kernel, per_launch_s, N, wl):
             roof = {"bound": "mfma", "achieved": flops / per_launch_s / 1e12,
                     "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s"}
     elif kernel == "states_lin":
-        work = N * state_walk_ops(wl.Hprime, wl.gamma)
+        work = N * state_walk_ops(wl.Hprime, wl.gamma, wl.model)
+        roof = {"bound": "alu", "achieved": work / per_launch_s / 1e12,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
+    elif kernel == "states_max":
+        work = N * max_walk_ops(wl.D, wl.Hprime, wl.gamma, stats=True)
         roof = {"bound": "alu", "achieved": work / per_launch_s / 1e12,
                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
     else:
@@ -245,8 +335,8 @@ def roofline(kernel, per_launch_s, N, wl):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_project_select_bsc256.md")
 KERNEL_SOURCES = {"project_select": ["paper_1908_06843_amd/csrc/k_project.hip",
-                                     "paper_1908_06843_amd/csrc/dev_common.hpp",
-                                     "paper_1908_06843_amd/csrc/prosper_internal.hpp"]}
+                                     "paper_1908_06843_amd/csrc/k_select.hpp",
+                                     "paper_1908_06843_amd/csrc/dev_common.hpp"]}
 
 
 def kernel_source_hash(kernel):
@@ -279,8 +369,9 @@ def measured_traffic(kernel):
 
 def pmc_pass():
     """Short run for hardware-counter passes: one device copy of a known size
-    (the scale reference for the byte counters), then two BF16 E-steps with
-    statistics at BSC scale."""
+    (the scale reference for the byte counters), two BF16 E-steps with
+    statistics at BSC scale, then one E-step with statistics on each of the
+    MCA and TSC workloads."""
     import torch
     import synth
     from paper_1908_06843_amd import api
@@ -300,6 +391,16 @@ def pmc_pass():
         api.estep(Yd, Wd, pi0, s0, Hprime=wl.Hprime, gamma=wl.gamma, precision="bf16", acc=acc,
                   want=(), ctx=ctx)
     torch.cuda.synchronize()
+    # one E-step with statistics on each of the MCA and TSC workloads
+    for name, prec in (("mca", "fp32"), ("tsc", "bf16")):
+        w2 = synth.WORKLOADS[name]
+        Y2, _, _, _ = synth.make_workload(name)
+        W2, p2, s2 = synth.initial_params(w2, Y2)
+        acc2 = api.new_acc(w2.model, w2.D, w2.H)
+        api.estep(torch.tensor(Y2, device=dev), torch.tensor(W2, device=dev), p2, s2,
+                  Hprime=w2.Hprime, gamma=w2.gamma, model=w2.model, precision=prec, acc=acc2,
+                  want=(), ctx=ctx)
+    torch.cuda.synchronize()
     print(json.dumps({"pmc_pass": "done", "copy_bytes": int(Yd.numel() * 4),
                       "project_select_source_hash": kernel_source_hash("project_select")}),
           flush=True)
@@ -313,7 +414,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the MCA, TSC and bars workloads")
+    ap.add_argument("--side-steps", type=int, default=10)
+    ap.add_argument("--side-cpu-seconds", type=float, default=6.0)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for rocprofv3 counter passes (no JSON metric line)")
@@ -355,10 +460,10 @@ def main():
     cpu = None
     err = {}
     if not args.no_cpu:
-        idx, ref, wall, cores = cpu_oracle_baseline(Y, W0, pi0, s0, wl.Hprime, wl.gamma,
+        idx, ref, wall, cores = cpu_oracle_baseline("bsc", Y, W0, pi0, s0, wl.Hprime, wl.gamma,
                                                     args.cpu_seconds)
         cpu = {"value": len(idx) * K / wall, "unit": "joint evals/s", "cores": cores,
-               "kind": "oracle",
+               "kind": "oracle", "cpu": cpu_model(),
                "sample": f"{len(idx)} of {Y.shape[0]} points (seeded), full E-step per point, "
                          f"{wall:.1f} s wall on {cores} processes x 1 BLAS thread"}
         for prec in res:
@@ -375,6 +480,11 @@ def main():
     per_launch_s = prof[dom]["ms"] / prof[dom]["launches"] * 1e-3
     N = Y.shape[0]
     roof = roofline(dom, per_launch_s, N, wl)
+    side = None
+    if not args.no_side:
+        side = {name: side_workload(name, np, torch, api, ctx, args.side_steps, 2,
+                                    args.side_cpu_seconds, args.no_cpu)
+                for name in ("mca", "tsc", "bars")}
     serving = None
     if not args.no_serve:
         serving = {p: serving_bench(np, api, args.serve_requests, p) for p in ("bf16", "fp32")}
@@ -402,6 +512,7 @@ def main():
                                     for k, v in r["profile"].items()},
                       "error_vs_fp64_oracle": err.get(p)} for p, r in res.items()},
         "serving": serving,
+        "other_workloads": side,
     }
     if "fp32" in res:
         line["bf16_speedup_over_fp32"] = res["fp32"]["ms_per_step"] / ms
