@@ -262,7 +262,7 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
   }
   if (is_max_model(a->model)) {
     const size_t lds = states_max_lds_bytes(a->Hprime, a->D, ns, a->accumulate != 0);
-    if (lds > 150 * 1024) {
+    if (lds > 150 * 1024 && !has_max_tree(a->Hprime, a->gamma, a->D, a->H)) {
       *msg = "MCA shape (Hprime x D and |K|) exceeds the per-workgroup LDS of this build";
       return PROSPER_EINVAL;
     }
@@ -441,6 +441,7 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
                has_tree_kernel(a->model, Hp, a->gamma) &&
                (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
   L.partB_floats = L.tree_acc ? (size_t)num_cu * stats_bslice_floats() : L.plan.partB_floats;
+  L.max_acc = a->accumulate && is_max_model(a->model) && has_max_tree(Hp, a->gamma, D, H);
   size_t sb = 0;
   auto add = [&](size_t n) { sb = ((sb + 255) & ~(size_t)255) + n; };
   add(L.need_sel ? (size_t)N * Hp * 4 : 0);
@@ -453,6 +454,7 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
   add(L.lin_acc && !L.tree_acc ? L.npairs * N * 4 : 0);
   add(L.lin_acc ? L.plan.partA_floats * 4 : 0);
   add(L.lin_acc ? L.partB_floats * 4 : 0);
+  add(L.max_acc ? max_tree_acc_floats(D, H) * 4 : 0);
   L.bytes = sb;
   return L;
 }
@@ -476,6 +478,7 @@ Scratch carve_estep(void* base, const EstepLayout& L, const prosper_args* a,
   if (!(L.lin_acc && !L.tree_acc)) sc.ss = nullptr;
   sc.partA = cv.take<float>(L.lin_acc ? L.plan.partA_floats : 0);
   sc.partB = cv.take<float>(L.lin_acc ? L.partB_floats : 0);
+  sc.max_acc = L.max_acc ? cv.take<float>(max_tree_acc_floats(a->D, a->H)) : nullptr;
   sc.plan = L.plan;
   sc.sel = L.need_sel ? sel_ws : out->sel;
   sc.s_mean = L.need_sm ? sm_ws : out->s_mean;

@@ -272,8 +272,10 @@ hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int
                              const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, float* A_num, float* B_den, double* scal,
                              hipStream_t st) {
-  (void)gamma;
   if (N <= 0) return hipSuccess;
+  if (has_max_tree(Hp, gamma, D, H) && (A_num == nullptr || s.max_acc != nullptr))
+    return launch_states_max_tree(model, Hp, gamma, N, D, Dp, H, tab_act, Y, p, s, logL,
+                                  top_mask, top_q, topk, A_num, B_den, scal, st);
   const size_t lds = states_max_lds_bytes(Hp, D, nstates, A_num != nullptr);
   const bool mag = model == PROSPER_MMCA;
   const auto kern = mag ? k_states_max<true> : k_states_max<false>;

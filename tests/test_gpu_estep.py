@@ -100,6 +100,11 @@ def test_topk_matches_oracle(model, name, N, Hp, gamma):
     g = gpu_estep(model, "fp32", Y, W, pi, sigma, Hp, gamma, topk=topk)
     act, sgn = O.state_masks(model, Hp, gamma)
     r = O.estep(model, Y, W, pi, sigma, Hp, gamma, topk=topk)
+    # a single state's q inherits the FP32 rounding of its log-joint
+    # (|lj| 2^-24 ~ 1e-5 at |lj| ~ 200 log2 units): 3e-5 relative.  The
+    # max-superposition walk sums its residual directly over the D pixels
+    # (per lane, then across 16 lanes): up to ~15 roundings of |lj|, 1e-4.
+    rq = 1e-4 if model == "mca" else 3e-5
     checked = 0
     for n in range(N):
         if r["flagged"][n] or not np.array_equal(g["sel"][n], r["sel"][n]):
@@ -111,13 +116,11 @@ def test_topk_matches_oracle(model, name, N, Hp, gamma):
             qmap[key] = p["q"][i]
         for t in range(topk):
             q_ref = r["top_q"][n, t]
-            # a single state's q inherits the FP32 rounding of its log-joint
-            # (|lj| 2^-24 ~ 1e-5 at |lj| ~ 200 log2 units): 3e-5 relative
-            assert abs(g["top_q"][n, t] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
+            assert abs(g["top_q"][n, t] - q_ref) <= rq * max(q_ref, 1e-3) + 1e-7
             key = ((int(g["top_mask"][n, t, 0]) & 0xffffffff, int(g["top_mask"][n, t, 1]) & 0xffffffff)
                    if model == "tsc" else int(g["top_mask"][n, t]) & 0xffffffff)
             # the GPU's t-th state has the oracle probability of rank t (ties allowed)
-            assert abs(qmap[key] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
+            assert abs(qmap[key] - q_ref) <= rq * max(q_ref, 1e-3) + 1e-7
         checked += 1
     assert checked > 0.9 * N
 
@@ -155,7 +158,9 @@ def test_annealed_posterior_matches_oracle(model, name, N, Hp, gamma, beta):
     r = O.estep(model, Y, W, pi, sigma, Hp, gamma, topk=3, beta=beta)
     assert_parity(g, r, "fp32", f"annealed {name} beta={beta}")
     ok = ~np.asarray(r["flagged"], dtype=bool)
-    np.testing.assert_allclose(g["top_q"][ok], r["top_q"][ok], rtol=3e-5, atol=1e-7)
+    # single-state q: the FP32 rounding of its log-joint (see the top-k test)
+    rq = 1e-4 if model == "mca" else 3e-5
+    np.testing.assert_allclose(g["top_q"][ok], r["top_q"][ok], rtol=rq, atol=1e-7)
     B = g["B"]
     if model != "mca":
         B = np.triu(B) + np.triu(B, 1).T
