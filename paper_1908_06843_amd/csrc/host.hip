@@ -442,6 +442,7 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
                (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
   L.partB_floats = L.tree_acc ? (size_t)num_cu * stats_bslice_floats() : L.plan.partB_floats;
   L.max_acc = a->accumulate && is_max_model(a->model) && has_max_tree(Hp, a->gamma, D, H);
+  L.max_parts = num_cu;
   size_t sb = 0;
   auto add = [&](size_t n) { sb = ((sb + 255) & ~(size_t)255) + n; };
   add(L.need_sel ? (size_t)N * Hp * 4 : 0);
@@ -454,7 +455,7 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
   add(L.lin_acc && !L.tree_acc ? L.npairs * N * 4 : 0);
   add(L.lin_acc ? L.plan.partA_floats * 4 : 0);
   add(L.lin_acc ? L.partB_floats * 4 : 0);
-  add(L.max_acc ? max_tree_acc_floats(D, H) * 4 : 0);
+  add(L.max_acc ? max_tree_acc_floats(D, H, L.max_parts) * 4 : 0);
   L.bytes = sb;
   return L;
 }
@@ -478,7 +479,8 @@ Scratch carve_estep(void* base, const EstepLayout& L, const prosper_args* a,
   if (!(L.lin_acc && !L.tree_acc)) sc.ss = nullptr;
   sc.partA = cv.take<float>(L.lin_acc ? L.plan.partA_floats : 0);
   sc.partB = cv.take<float>(L.lin_acc ? L.partB_floats : 0);
-  sc.max_acc = L.max_acc ? cv.take<float>(max_tree_acc_floats(a->D, a->H)) : nullptr;
+  sc.max_acc = L.max_acc ? cv.take<float>(max_tree_acc_floats(a->D, a->H, L.max_parts)) : nullptr;
+  sc.max_parts = L.max_acc ? L.max_parts : 0;
   sc.plan = L.plan;
   sc.sel = L.need_sel ? sel_ws : out->sel;
   sc.s_mean = L.need_sm ? sm_ws : out->s_mean;

@@ -14,18 +14,26 @@
 //    its prefix's by one max per pixel;
 //  * per state every lane holds the partial residual over its pixels; a
 //    butterfly reduce-scatter over 16 states at a time (DPP within each row
-//    of 16 lanes) leaves the full sum of state 16 b + l in lane l;
-//  * responsibilities: a second enumeration decides per pixel which slot of
-//    the state attains the maximum (the lower slot on ties) and adds q(s) to
-//    that slot's register accumulator.  States whose posterior weight is
-//    below 2^-40 of the largest at every point of the wave are skipped there:
-//    their total contribution to any responsibility is below 176 * 2^-40,
-//    far under the FP32 rounding of the sums they would enter;
-//  * the per-point responsibilities leave through coalesced atomics into a
-//    transposed (H x Dq) copy of the accumulators, added to A and B in their
-//    D x H layout at the end of the call.
-// Waves are independent (no workgroup barrier): each owns its LDS rows of
-// log-joints and residuals.
+//    of 16 lanes) leaves the full sum of state 16 b + l in lane l, which
+//    keeps that state's log-joint and residual in register b;
+//  * responsibilities: a second walk over the subset tree decides per pixel
+//    which slot of a state attains the maximum (the lower slot on ties) and
+//    adds q(s) to that slot's register accumulator, q(s) broadcast from its
+//    owner lane by DPP.  Childless states whose posterior weight is below
+//    2^-40 of the largest at every point of the wave are skipped: their total
+//    contribution to any responsibility is below |K| 2^-40, far under the
+//    FP32 rounding of the sums they would enter;
+//  * the per-point responsibilities are summed per workgroup in LDS (one
+//    workgroup per CU holding A and B of the latents that fit, transposed)
+//    as 32-bit fixed-point integers, whose LDS atomics run at the rate of
+//    plain LDS traffic where float ones do not.  A window of W <= 480 points
+//    adds at most W terms to a sum; terms are rounded at the power-of-two
+//    scales that keep W of them within uint32 (B: R in [0, 1]; error below
+//    W 2^-32) and int32 (A: R y, |y| <= ymax, the largest |y_nd| of the call;
+//    error below W ymax 2^-31).  After every window a workgroup adds its
+//    LDS sums into its own int64 partial (exact), and a second kernel adds
+//    the partials and scales them back; latents beyond what LDS holds go
+//    through global float atomics.
 #include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
@@ -146,22 +154,22 @@ struct Enum {
   }
 };
 
-// Pass 1: residual of every state, reduce-scattered 16 states at a time.
+// Pass 1: residual of every state, reduce-scattered 16 states at a time;
+// lane l keeps log-joint and residual of state 16 b + l in lj[b], rs[b].
 template <int HP, int GAMMA, bool MAG, int NPIX>
 struct Pass1 {
   static constexpr int NS = nstates_c(HP, GAMMA);
+  static constexpr int NB = (NS + 15) / 16;
   const float (&y)[NPIX];
-  float* ljs;  // this point's row
-  float* Rs;
   int l;
   bool up8, up4, up2, up1;
   float c1, lam2;
   float mx;
   float pt[16];
+  float lj[NB], rs[NB];
 
-  __device__ __forceinline__ Pass1(const float (&y_)[NPIX], float* ljs_, float* Rs_, int l_,
-                                   float c1_, float lam2_)
-      : y(y_), ljs(ljs_), Rs(Rs_), l(l_), c1(c1_), lam2(lam2_), mx(-INFINITY) {
+  __device__ __forceinline__ Pass1(const float (&y_)[NPIX], int l_, float c1_, float lam2_)
+      : y(y_), l(l_), c1(c1_), lam2(lam2_), mx(-INFINITY) {
     up8 = (l & 8) != 0;
     up4 = (l & 4) != 0;
     up2 = (l & 2) != 0;
@@ -173,7 +181,6 @@ struct Pass1 {
   template <unsigned MASK>
   __device__ __forceinline__ void leaf(const float (&f)[NPIX]) {
     constexpr int c = canon_c(HP, MASK);
-    __builtin_amdgcn_sched_barrier(0);
     float part = 0.0f;
 #pragma unroll
     for (int i = 0; i < NPIX; ++i) {
@@ -195,22 +202,26 @@ struct Pass1 {
     rs_stage<2, DPP_XOR2>(pt, up2);
     rs_stage<1, DPP_XOR1>(pt, up1);
     const int t = B * 16 + l;
-    if (t < NS) {
-      // number of actives of canonical state t
-      int k = 0;
-      static_for<1, GAMMA + 1>([&](auto kc) {
-        constexpr int kk = decltype(kc)::value;
-        k += t >= nstates_c(HP, kk - 1) ? 1 : 0;
-      });
-      const float lj = (float)k * c1 - lam2 * pt[0];
-      Rs[t] = pt[0];
-      ljs[t] = lj;
-      mx = fmaxf(mx, lj);
-    }
+    // number of actives of canonical state t
+    int k = 0;
+    static_for<1, GAMMA + 1>([&](auto kc) {
+      constexpr int kk = decltype(kc)::value;
+      k += t >= nstates_c(HP, kk - 1) ? 1 : 0;
+    });
+    const bool live = (B + 1) * 16 <= NS || t < NS;
+    lj[B] = live ? (float)k * c1 - lam2 * pt[0] : -INFINITY;
+    rs[B] = live ? pt[0] : 0.0f;
+    mx = fmaxf(mx, lj[B]);
 #pragma unroll
     for (int i = 0; i < 16; ++i) pt[i] = 0.0f;
   }
 };
+
+// Lane n of each row of 16 to the whole row (row_newbcast).
+template <int N>
+__device__ __forceinline__ float row_bcast(float v) {
+  return dppf<0x150 + N>(v);
+}
 
 // Pass 2: responsibilities, walking the subset tree depth first (children
 // of S add one slot above S's last).  The winner of a state at a pixel is
@@ -222,28 +233,26 @@ struct Pass1 {
 //   U(S) = sum over children c = S + j of [j does not beat b_S] (q(c) + U(c))
 //   R[j] += [j beats b_S] (q(c) + U(c))
 // and U(root) is dropped (no winner).
-template <int HP, int NPIX>
+template <int HP, int NPIX, int NB>
 struct Pass2 {
-  const float* q;  // this point's row of posterior weights
+  float q[NB];  // lane l: posterior weight of state 16 b + l
   float thr;
   float R[HP][NPIX];
+  template <int C>
+  __device__ __forceinline__ float weight() const {
+    return row_bcast<C % 16>(q[C / 16]);
+  }
 };
 
 template <int HP, int GAMMA, int NPIX, bool MAG, int DEPTH, int LAST, unsigned MASK>
 struct Resp {
+  template <class V>
   static __device__ __forceinline__ void run(const float (&P)[HP][NPIX], const float (&b)[NPIX],
-                                             float (&U)[NPIX], Pass2<HP, NPIX>& v) {
-    // the weights of all children first: one LDS round trip per node
-    float qc[HP];
-    static_for<LAST + 1, HP>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      qc[j] = v.q[canon_c(HP, MASK | (1u << j))];
-    });
+                                             float (&U)[NPIX], V& v) {
     static_for<LAST + 1, HP>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
       constexpr unsigned CM = MASK | (1u << j);
-      const float qs = qc[j];
-      __builtin_amdgcn_sched_barrier(0);
+      const float qs = v.template weight<canon_c(HP, CM)>();
       if constexpr (DEPTH + 1 < GAMMA && j + 1 < HP) {
         float bc[NPIX], Uc[NPIX];
 #pragma unroll
@@ -282,50 +291,96 @@ struct Resp {
 
 }  // namespace
 
+// Fixed-point statistics: at most 15 sweeps (of 32 points) per window.  A
+// window of wpts points adds at most wpts terms to one sum, each |R y| <=
+// ymax (A) or R <= 1 (B); the scales are the largest powers of two that keep
+// wpts such terms within int32 (A) or uint32 (B).
+static constexpr int MAXTREE_WIN_SWEEPS = 15;
+__host__ __device__ __forceinline__ float pow2_floor(float x) {
+  int e;
+  frexpf(x, &e);  // x = m 2^e, m in [0.5, 1)
+  return ldexpf(1.0f, e - 1);
+}
+__device__ __forceinline__ float maxtree_scale_a(float ymax, int wpts) {
+  if (!(ymax > 0.0f)) return 16777216.0f;
+  return pow2_floor(2147483647.0f / ((float)wpts * ymax));
+}
+static float maxtree_scale_b(int wpts) { return pow2_floor(4294967295.0f / (float)wpts); }
+// Adds the workgroup's LDS sums into its int64 partial (stores on the first
+// window) and clears them.
+__device__ __forceinline__ void maxtree_flush(unsigned* acc_lds, int nacc, long long* dst,
+                                              bool add) {
+  __syncthreads();
+  const int half = nacc / 2;
+  for (int i = threadIdx.x; i < nacc; i += 512) {
+    const unsigned v = acc_lds[i];
+    const long long x = i < half ? (long long)(int)v : (long long)v;  // A signed, B unsigned
+    dst[i] = add ? dst[i] + x : x;
+    acc_lds[i] = 0u;
+  }
+  __syncthreads();
+}
+
+// One workgroup of 8 waves; with statistics, one workgroup per CU holding
+// the LDS sums [A | B][HL][D] of latents < HL.
 template <int HP, int GAMMA, bool MAG, int NPIX>
-__global__ __launch_bounds__(256) void k_states_maxtree(
+__global__ __launch_bounds__(512) void k_states_maxtree(
     const float* __restrict__ Y, int64_t N, int D, int Dp, const float* __restrict__ Pt32,
     const int32_t* __restrict__ sel, const uint32_t* __restrict__ tab_act,
     const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
-    uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk,
+    uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk, int accum, int HL,
+    const float* __restrict__ ymax_p, int wpts, float sB, long long* __restrict__ part,
     float* __restrict__ AT, float* __restrict__ BT, int Dq, double* __restrict__ scal) {
   constexpr int NS = nstates_c(HP, GAMMA);
-  constexpr int NSP = NS | 1;  // odd row stride: the four points of a wave hit distinct banks
-  __shared__ float lds_lj[4][4][NSP];
-  __shared__ float lds_R[4][4][NSP];
+  constexpr int NB = (NS + 15) / 16;
+  extern __shared__ unsigned acc_lds[];  // [A | B][HL][D], fixed point
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, l = lane & 15;
-  float* ljs = lds_lj[wave][g];
-  float* Rs = lds_R[wave][g];
   const float c1 = th->c1_2, lam2 = th->lam2, beta = th->beta;
+  const int nacc = 2 * HL * D;
+  const bool lds_acc = accum && HL > 0;
+  const float sA = accum ? maxtree_scale_a(*ymax_p, wpts) : 0.0f;
+  if (lds_acc) {
+    for (int i = threadIdx.x; i < nacc; i += 512) acc_lds[i] = 0u;
+    __syncthreads();
+  }
   double acc_k = 0.0, acc_l = 0.0, acc_r = 0.0;
+  int windows = 0;
 
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 4; base < N;
-       base += (int64_t)gridDim.x * 16) {
+  // the sweep count is uniform over the workgroup (the window barriers)
+  for (int64_t sweep = (int64_t)blockIdx.x * 32, k = 0; sweep < N;
+       sweep += (int64_t)gridDim.x * 32, ++k) {
+    if (lds_acc && k > 0 && k % MAXTREE_WIN_SWEEPS == 0) {
+      maxtree_flush(acc_lds, nacc, part + (int64_t)blockIdx.x * nacc, windows > 0);
+      ++windows;
+    }
+    const int64_t base = sweep + wave * 4;
+    if (base >= N) continue;  // past the end: nothing for this wave in the sweep
     const int64_t n = base + g;
     const bool valid = n < N;
     const int64_t nn = valid ? n : N - 1;
     float y[NPIX];
     float P[HP][NPIX];
-    int hsel[HP];
+    {
+      int hsel[HP];
 #pragma unroll
-    for (int j = 0; j < HP; ++j) hsel[j] = sel[nn * HP + j];
+      for (int j = 0; j < HP; ++j) hsel[j] = sel[nn * HP + j];
 #pragma unroll
-    for (int i = 0; i < NPIX; ++i) {
-      const int d = l + 16 * i;
-      y[i] = d < D ? Y[nn * D + d] : 0.0f;
+      for (int i = 0; i < NPIX; ++i) {
+        const int d = l + 16 * i;
+        y[i] = d < D ? Y[nn * D + d] : 0.0f;
+      }
+      // rows of P are zero beyond D and at least 16 NPIX long
+#pragma unroll
+      for (int j = 0; j < HP; ++j)
+#pragma unroll
+        for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
     }
-    // rows of P are zero beyond D and at least 16 NPIX long
-#pragma unroll
-    for (int j = 0; j < HP; ++j)
-#pragma unroll
-      for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
 
     // ---- pass 1: log-joints (log2 units) and residuals of every state
-    float mx;
+    Pass1<HP, GAMMA, MAG, NPIX> p1(y, l, c1, lam2);
     {
-      Pass1<HP, GAMMA, MAG, NPIX> p1(y, ljs, Rs, l, c1, lam2);
       float zero[NPIX];
 #pragma unroll
       for (int i = 0; i < NPIX; ++i) zero[i] = 0.0f;
@@ -341,15 +396,12 @@ __global__ __launch_bounds__(256) void k_states_maxtree(
           for (int i = 0; i < NPIX; ++i) asm volatile("" : "+v"(P[j][i]));
         Enum<HP, NPIX, MAG, K, 0, -1, 0u>::run(P, zero, p1);
       });
-      mx = p1.mx;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const float m = row_max16(mx);
+    const float m = row_max16(p1.mx);
     float z = 0.0f, z1 = 0.0f;
-    for (int t = l; t < NS; t += 16) {
-      const float dd = ljs[t] - m;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const float dd = p1.lj[b] - m;  // -inf for the padding entries
       z1 += __builtin_amdgcn_exp2f(dd);
       z += beta == 1.0f ? __builtin_amdgcn_exp2f(dd) : __builtin_amdgcn_exp2f(beta * dd);
     }
@@ -364,10 +416,12 @@ __global__ __launch_bounds__(256) void k_states_maxtree(
       for (int t = 0; t < topk; ++t) {
         float v = -INFINITY;
         int id = 0x7fffffff;
-        for (int k = l; k < NS; k += 16) {
-          const float x = ljs[k];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int k = 16 * b + l;
+          const float x = p1.lj[b];
           const bool below = (x < pv) || (x == pv && k > pid);
-          if (below && (x > v || id == 0x7fffffff)) {
+          if (k < NS && below && (x > v || id == 0x7fffffff)) {
             v = x;
             id = k;
           }
@@ -384,22 +438,22 @@ __global__ __launch_bounds__(256) void k_states_maxtree(
         pid = id;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // ---- q, moments, expected residual
+    Pass2<HP, NPIX, NB> p2;
     float res = 0.0f;
     float sm[HP];
 #pragma unroll
     for (int j = 0; j < HP; ++j) sm[j] = 0.0f;
-    for (int t = l; t < NS; t += 16) {
-      const float qv = __builtin_amdgcn_exp2f(beta * (ljs[t] - m)) * invZ;
-      res = __builtin_fmaf(qv, Rs[t], res);
-      const uint32_t act = tab_act[t];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int t = 16 * b + l;
+      const float qv = __builtin_amdgcn_exp2f(beta * (p1.lj[b] - m)) * invZ;  // 0 on padding
+      res = __builtin_fmaf(qv, p1.rs[b], res);
+      const uint32_t act = t < NS ? tab_act[t] : 0u;
 #pragma unroll
       for (int j = 0; j < HP; ++j) sm[j] += ((act >> j) & 1u) ? qv : 0.0f;
-      ljs[t] = qv;
+      p2.q[b] = qv;
     }
     float kmean = 0.0f;
 #pragma unroll
@@ -428,30 +482,25 @@ __global__ __launch_bounds__(256) void k_states_maxtree(
       acc_l += lL;
       acc_r += (double)resid + yy_n;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // ---- pass 2: responsibilities, into the transposed accumulators
-    if (AT) {
-      Pass2<HP, NPIX> p2;
-      p2.q = ljs;
-      // 2^-40 of the largest weight of this point (1/Z is the weight of the
-      // best state at beta = 1; the best state's weight in general)
+    // ---- pass 2: responsibilities
+    if (accum) {
+      // P read again (from L2): nothing of pass 1 stays live across the
+      // log-sum-exp, and value numbering cannot carry pass 1's maxima over
+      // to the equal ones here
+      int hsel[HP];
+#pragma unroll
+      for (int j = 0; j < HP; ++j) {
+        hsel[j] = sel[nn * HP + j];
+#pragma unroll
+        for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
+      }
+      // 2^-40 of the largest weight of this point (1/Z: the best state's)
       p2.thr = valid ? 0x1p-40f * invZ : INFINITY;
 #pragma unroll
       for (int j = 0; j < HP; ++j)
 #pragma unroll
         for (int i = 0; i < NPIX; ++i) p2.R[j][i] = 0.0f;
-      // P read again (from L2): nothing of pass 1 stays live across the
-      // log-sum-exp, and value numbering cannot carry pass 1's maxima over
-      // to the equal ones here
-#pragma unroll
-      for (int j = 0; j < HP; ++j) {
-        asm volatile("" : "+v"(hsel[j]));
-#pragma unroll
-        for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
-      }
       float b0[NPIX], U0[NPIX];
 #pragma unroll
       for (int i = 0; i < NPIX; ++i) {
@@ -462,31 +511,89 @@ __global__ __launch_bounds__(256) void k_states_maxtree(
       if (valid) {
 #pragma unroll
         for (int j = 0; j < HP; ++j) {
-          // keeps the addresses from being formed (and held) before the walks
-          asm volatile("" : "+v"(hsel[j]));
-          float* at = AT + (int64_t)hsel[j] * Dq;
-          float* bt = BT + (int64_t)hsel[j] * Dq;
+          const int h = hsel[j];
+          if (h < HL) {
+            unsigned* la = acc_lds + h * D;
+            unsigned* lb = acc_lds + (HL + h) * D;
 #pragma unroll
-          for (int i = 0; i < NPIX; ++i) {
-            const int d = l + 16 * i;
-            const float r = p2.R[j][i];
-            if (d < D && r != 0.0f) {
-              atomicAdd(at + d, r * y[i]);
-              atomicAdd(bt + d, r);
+            for (int i = 0; i < NPIX; ++i) {
+              const int d = l + 16 * i;
+              const float r = p2.R[j][i];
+              if (d < D && r != 0.0f) {
+                // two's complement: the int32 sum is the wrapped u32 sum
+                atomicAdd(la + d, (unsigned)__float2int_rn(r * y[i] * sA));
+                atomicAdd(lb + d, __float2uint_rn(r * sB));
+              }
+            }
+          } else {
+            float* at = AT + (int64_t)(h - HL) * Dq;
+            float* bt = BT + (int64_t)(h - HL) * Dq;
+#pragma unroll
+            for (int i = 0; i < NPIX; ++i) {
+              const int d = l + 16 * i;
+              const float r = p2.R[j][i];
+              if (d < D && r != 0.0f) {
+                atomicAdd(at + d, r * y[i]);
+                atomicAdd(bt + d, r);
+              }
             }
           }
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (scal && l == 0) {
     atomicAdd(&scal[0], acc_k);
     atomicAdd(&scal[1], acc_l);
     atomicAdd(&scal[3], acc_r);
   }
+  if (lds_acc) maxtree_flush(acc_lds, nacc, part + (int64_t)blockIdx.x * nacc, windows > 0);
+}
+
+// A[d][h] += sum over workgroups of the partials (latents < HL), scaled back.
+// Each block takes 64 entries; its four waves sum a quarter of the
+// workgroup partials each.
+__global__ __launch_bounds__(256) void k_reduce_parts(const long long* __restrict__ part,
+                                                      int nparts, int HL, int D, int H,
+                                                      const float* __restrict__ ymax_p, int wpts,
+                                                      float sB, float* __restrict__ A,
+                                                      float* __restrict__ B) {
+  __shared__ long long red[4][64];
+  const int nacc = 2 * HL * D;
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  long long s0 = 0, s1 = 0;
+  if (e < nacc) {
+    int w = q;
+    for (; w + 4 < nparts; w += 8) {
+      s0 += part[(int64_t)w * nacc + e];
+      s1 += part[(int64_t)(w + 4) * nacc + e];
+    }
+    if (w < nparts) s0 += part[(int64_t)w * nacc + e];
+  }
+  red[q][threadIdx.x & 63] = s0 + s1;
+  __syncthreads();
+  if (q == 0 && e < nacc) {
+    const long long tot = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                          red[3][threadIdx.x];
+    const int which = e / (HL * D);
+    const int r = e - which * HL * D;
+    const int h = r / D, d = r - h * D;
+    const double inv = which ? 1.0 / (double)sB : 1.0 / (double)maxtree_scale_a(*ymax_p, wpts);
+    float* dst = which ? B : A;
+    dst[(int64_t)d * H + h] += (float)((double)tot * inv);
+  }
+}
+
+// max |y| over the batch into *ymax (cleared beforehand), as the order-
+// preserving bit pattern of a non-negative float.
+__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ Y, int64_t n,
+                                                float* __restrict__ ymax) {
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(Y[i]));
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned*>(ymax), __float_as_uint(m));
 }
 
 // Fill of the transposed accumulators (a kernel, so that the call can be
@@ -496,26 +603,28 @@ __global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_
     p[i] = 0.0f;
 }
 
-// A[d][h] += AT[h][d], B[d][h] += BT[h][d].
+// A[d][HL + h] += AT[h][d], B[d][HL + h] += BT[h][d] for h < H - HL.
 __global__ __launch_bounds__(256) void k_add_transposed(const float* __restrict__ AT,
                                                         const float* __restrict__ BT, int Dq,
-                                                        int D, int H, float* __restrict__ A,
+                                                        int D, int H, int HL,
+                                                        float* __restrict__ A,
                                                         float* __restrict__ B) {
   __shared__ float ta[32][33], tb[32][33];
+  const int HR = H - HL;
   const int h0 = blockIdx.x * 32, d0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int r = ty; r < 32; r += 8) {
     const int h = h0 + r, d = d0 + tx;
-    const bool ok = h < H && d < D;
+    const bool ok = h < HR && d < D;
     ta[r][tx] = ok ? AT[(int64_t)h * Dq + d] : 0.0f;
     tb[r][tx] = ok ? BT[(int64_t)h * Dq + d] : 0.0f;
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int d = d0 + r, h = h0 + tx;
-    if (d < D && h < H) {
-      A[(int64_t)d * H + h] += ta[tx][r];
-      B[(int64_t)d * H + h] += tb[tx][r];
+    if (d < D && h < HR) {
+      A[(int64_t)d * H + HL + h] += ta[tx][r];
+      B[(int64_t)d * H + HL + h] += tb[tx][r];
     }
   }
 }
@@ -540,18 +649,33 @@ bool has_max_tree(int Hp, int gamma, int D, int H) {
   return false;
 }
 
-size_t max_tree_acc_floats(int D, int H) { return 2 * (size_t)H * round_up(D, 16); }
+// LDS of the statistics workgroups: 160 KB, of which the sums take what fits.
+static constexpr int MAXTREE_LDS_FLOATS = 160 * 1024 / 4;
+static int maxtree_hl(int D, int H) {
+  const int hl = MAXTREE_LDS_FLOATS / (2 * D);
+  return hl < H ? hl : H;
+}
+
+// Scratch of the statistics (in floats): ymax (64), the int64 workgroup
+// partials, the transposed float sums of the latents beyond LDS.
+size_t max_tree_acc_floats(int D, int H, int nparts) {
+  const int HL = maxtree_hl(D, H);
+  return 64 + (size_t)nparts * 2 * HL * D * 2 + 2 * (size_t)(H - HL) * round_up(D, 16);
+}
 
 template <int HP, int GAMMA, bool MAG, int NPIX>
 static hipError_t launch_mt(const float* Y, int64_t N, int D, int Dp, const Prepared& p,
                             const Scratch& s, const uint32_t* tab_act, float* logL,
-                            uint32_t* top_mask, float* top_q, int topk, float* AT, float* BT,
-                            int Dq, double* scal, hipStream_t st) {
-  const int64_t quads = (N + 15) / 16;
-  const unsigned blocks = (unsigned)(quads < 4096 ? quads : 4096);
-  hipLaunchKernelGGL((k_states_maxtree<HP, GAMMA, MAG, NPIX>), dim3(blocks), dim3(256), 0, st, Y,
-                     N, D, Dp, p.Pt32, s.sel, tab_act, p.theta, s.s_mean, logL, top_mask, top_q,
-                     topk, AT, BT, Dq, scal);
+                            uint32_t* top_mask, float* top_q, int topk, int accum, int HL,
+                            int blocks, const float* ymax, int wpts, float sB, long long* part,
+                            float* AT, float* BT, int Dq, double* scal, hipStream_t st) {
+  auto kern = k_states_maxtree<HP, GAMMA, MAG, NPIX>;
+  const size_t lds = accum ? (size_t)2 * HL * D * 4 : 0;
+  hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+  if (e0 != hipSuccess) return e0;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(512), lds, st, Y, N, D, Dp, p.Pt32,
+                     s.sel, tab_act, p.theta, s.s_mean, logL, top_mask, top_q, topk, accum, HL,
+                     ymax, wpts, sB, part, AT, BT, Dq, scal);
   return hipGetLastError();
 }
 
@@ -564,41 +688,70 @@ hipError_t launch_states_max_tree(int model, int Hp, int gamma, int64_t N, int D
   const int npix = maxtree_npix(D);
   const bool mag = model == PROSPER_MMCA;
   const int Dq = round_up(D, 16);
-  float* AT = nullptr;
-  float* BT = nullptr;
-  if (A_num) {
-    if (!s.max_acc) return hipErrorInvalidValue;
-    AT = s.max_acc;
-    BT = AT + (size_t)H * Dq;
-    const int64_t nf = (int64_t)max_tree_acc_floats(D, H);
-    const int64_t fb = (nf + 255) / 256;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(fb < 1024 ? fb : 1024)), dim3(256), 0, st,
-                       AT, nf);
+  const int64_t groups = (N + 31) / 32;  // 32 points per workgroup and sweep
+  const int accum = A_num != nullptr ? 1 : 0;
+  int HL = 0, blocks, wpts = 32;
+  float sB = 0.0f;
+  float *ymax = nullptr, *AT = nullptr, *BT = nullptr;
+  long long* part = nullptr;
+  if (accum) {
+    if (!s.max_acc || s.max_parts <= 0) return hipErrorInvalidValue;
+    HL = maxtree_hl(D, H);
+    blocks = (int)(groups < s.max_parts ? groups : s.max_parts);
+    const int64_t sweeps = (groups + blocks - 1) / blocks;  // per workgroup
+    wpts = 32 * (int)(sweeps < MAXTREE_WIN_SWEEPS ? sweeps : MAXTREE_WIN_SWEEPS);
+    sB = maxtree_scale_b(wpts);
+    ymax = s.max_acc;
+    part = reinterpret_cast<long long*>(s.max_acc + 64);
+    AT = s.max_acc + 64 + (size_t)s.max_parts * 2 * HL * D * 2;
+    BT = AT + (size_t)(H - HL) * Dq;
+    // clear ymax and the float sums in one fill (they are contiguous but for
+    // the partials, which every workgroup stores before it adds)
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, st, ymax, (int64_t)64);
+    if (H > HL) {
+      const int64_t nf = 2 * (int64_t)(H - HL) * Dq;
+      const int64_t fb = (nf + 255) / 256;
+      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(fb < 1024 ? fb : 1024)), dim3(256), 0,
+                         st, AT, nf);
+    }
+    const int64_t ny = N * (int64_t)D;
+    const int64_t yb = (ny + 255) / 256;
+    hipLaunchKernelGGL(k_absmax, dim3((unsigned)(yb < 2048 ? yb : 2048)), dim3(256), 0, st, Y,
+                       ny, ymax);
+  } else {
+    blocks = (int)(groups < 2048 ? groups : 2048);
   }
   hipError_t e = hipErrorInvalidValue;
-#define X(HPV, GV)                                                                            \
-  if (Hp == HPV && gamma == GV) {                                                             \
-    if (npix == 4)                                                                            \
-      e = mag ? launch_mt<HPV, GV, true, 4>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q, \
-                                            topk, AT, BT, Dq, scal, st)                       \
-              : launch_mt<HPV, GV, false, 4>(Y, N, D, Dp, p, s, tab_act, logL, top_mask,      \
-                                             top_q, topk, AT, BT, Dq, scal, st);              \
-    else if (npix == 7)                                                                       \
-      e = mag ? launch_mt<HPV, GV, true, 7>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q, \
-                                            topk, AT, BT, Dq, scal, st)                       \
-              : launch_mt<HPV, GV, false, 7>(Y, N, D, Dp, p, s, tab_act, logL, top_mask,      \
-                                             top_q, topk, AT, BT, Dq, scal, st);              \
-    else if (npix == 8)                                                                       \
-      e = mag ? launch_mt<HPV, GV, true, 8>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q, \
-                                            topk, AT, BT, Dq, scal, st)                       \
-              : launch_mt<HPV, GV, false, 8>(Y, N, D, Dp, p, s, tab_act, logL, top_mask,      \
-                                             top_q, topk, AT, BT, Dq, scal, st);              \
+#define LAUNCH(HPV, GV, NP)                                                                    \
+  (mag ? launch_mt<HPV, GV, true, NP>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q, topk, \
+                                      accum, HL, blocks, ymax, wpts, sB, part, AT, BT, Dq,     \
+                                      scal, st)                                                \
+       : launch_mt<HPV, GV, false, NP>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q,      \
+                                       topk, accum, HL, blocks, ymax, wpts, sB, part, AT, BT,  \
+                                       Dq, scal, st))
+#define X(HPV, GV)                       \
+  if (Hp == HPV && gamma == GV) {        \
+    if (npix == 4)                       \
+      e = LAUNCH(HPV, GV, 4);            \
+    else if (npix == 7)                  \
+      e = LAUNCH(HPV, GV, 7);            \
+    else if (npix == 8)                  \
+      e = LAUNCH(HPV, GV, 8);            \
   }
   PROSPER_MAXTREE_SHAPES(X)
 #undef X
-  if (e != hipSuccess || !A_num) return e;
-  dim3 grid((unsigned)((H + 31) / 32), (unsigned)((D + 31) / 32));
-  hipLaunchKernelGGL(k_add_transposed, grid, dim3(256), 0, st, AT, BT, Dq, D, H, A_num, B_den);
+#undef LAUNCH
+  if (e != hipSuccess || !accum) return e;
+  if (HL > 0) {
+    const int nacc = 2 * HL * D;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((nacc + 63) / 64)), dim3(256), 0, st,
+                       part, blocks, HL, D, H, ymax, wpts, sB, A_num, B_den);
+  }
+  if (H > HL) {
+    dim3 grid((unsigned)((H - HL + 31) / 32), (unsigned)((D + 31) / 32));
+    hipLaunchKernelGGL(k_add_transposed, grid, dim3(256), 0, st, AT, BT, Dq, D, H, HL, A_num,
+                       B_den);
+  }
   return hipGetLastError();
 }
 

@@ -78,9 +78,12 @@ struct Scratch {
   float* defer = nullptr;
   int defer_cap = 0;
   int32_t* defer_count = nullptr;  // 1 (cleared by the parameter kernel of each call)
-  // MCA/MMCA statistics of the unrolled walk: A and B transposed (H x Dq each,
-  // Dq = D rounded up to 16), added into the caller's accumulators at the end
+  // MCA/MMCA statistics of the unrolled walk: max_parts workgroup sums of
+  // A and B (transposed, latents that fit in LDS), then A and B transposed
+  // for the other latents (rows of D rounded up to 16); reduced into the
+  // caller's accumulators at the end of the walk
   float* max_acc = nullptr;
+  int max_parts = 0;
   float* partA;         // statistics: per-group partials of A and B
   float* partB;
   StatsPlan plan;
@@ -188,7 +191,7 @@ prosper_status check_estep(const prosper_args* a, const float* Y, const float* W
 // Per-point workspace of one E-step call: which pieces it needs and its size.
 struct EstepLayout {
   bool need_sel = false, need_sm = false, lin_acc = false, tree_acc = false, max_acc = false;
-  int defer_cap = 0, Hpad = 0;
+  int defer_cap = 0, Hpad = 0, max_parts = 0;
   size_t npairs = 0, partB_floats = 0, bytes = 0;
   StatsPlan plan;
 };
@@ -214,7 +217,7 @@ prosper_status set_error(prosper_status st, const std::string& msg);
 bool has_tree_kernel(int model, int Hp, int gamma);
 // The same for max superposition (also depends on D and H).
 bool has_max_tree(int Hp, int gamma, int D, int H);
-size_t max_tree_acc_floats(int D, int H);
+size_t max_tree_acc_floats(int D, int H, int nparts);
 hipError_t launch_states_max_tree(int model, int Hp, int gamma, int64_t N, int D, int Dp, int H,
                                   const uint32_t* tab_act, const float* Y, const Prepared& p,
                                   const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
