@@ -25,15 +25,12 @@
 //    FP32 rounding of the sums they would enter;
 //  * the per-point responsibilities are summed per workgroup in LDS (one
 //    workgroup per CU holding A and B of the latents that fit, transposed)
-//    as 32-bit fixed-point integers, whose LDS atomics run at the rate of
-//    plain LDS traffic where float ones do not.  A window of W <= 480 points
-//    adds at most W terms to a sum; terms are rounded at the power-of-two
-//    scales that keep W of them within uint32 (B: R in [0, 1]; error below
-//    W 2^-32) and int32 (A: R y, |y| <= ymax, the largest |y_nd| of the call;
-//    error below W ymax 2^-31).  After every window a workgroup adds its
-//    LDS sums into its own int64 partial (exact), and a second kernel adds
-//    the partials and scales them back; latents beyond what LDS holds go
-//    through global float atomics.
+//    with FP32 LDS atomics; the workgroup sums are written out once and a
+//    second kernel adds them in FP64.  Latents beyond what LDS holds go
+//    through global float atomics.  (Exact fixed-point sums with integer
+//    LDS atomics run faster but lose the relative precision of the small
+//    sums that the M-step divides; a lock-ordered FP32 read-modify-write
+//    ran slower than the atomics.)
 #include "dev_common.hpp"
 #include "prosper_internal.hpp"
 
@@ -291,36 +288,9 @@ struct Resp {
 
 }  // namespace
 
-// Fixed-point statistics: at most 15 sweeps (of 32 points) per window.  A
-// window of wpts points adds at most wpts terms to one sum, each |R y| <=
-// ymax (A) or R <= 1 (B); the scales are the largest powers of two that keep
-// wpts such terms within int32 (A) or uint32 (B).
-static constexpr int MAXTREE_WIN_SWEEPS = 15;
-__host__ __device__ __forceinline__ float pow2_floor(float x) {
-  int e;
-  frexpf(x, &e);  // x = m 2^e, m in [0.5, 1)
-  return ldexpf(1.0f, e - 1);
-}
-__device__ __forceinline__ float maxtree_scale_a(float ymax, int wpts) {
-  if (!(ymax > 0.0f)) return 16777216.0f;
-  return pow2_floor(2147483647.0f / ((float)wpts * ymax));
-}
-static float maxtree_scale_b(int wpts) { return pow2_floor(4294967295.0f / (float)wpts); }
-// Adds the workgroup's LDS sums into its int64 partial (stores on the first
-// window) and clears them.
-__device__ __forceinline__ void maxtree_flush(unsigned* acc_lds, int nacc, long long* dst,
-                                              bool add) {
-  __syncthreads();
-  const int half = nacc / 2;
-  for (int i = threadIdx.x; i < nacc; i += 512) {
-    const unsigned v = acc_lds[i];
-    const long long x = i < half ? (long long)(int)v : (long long)v;  // A signed, B unsigned
-    dst[i] = add ? dst[i] + x : x;
-    acc_lds[i] = 0u;
-  }
-  __syncthreads();
-}
-
+// Adds the terms of this wave's points into the workgroup sums (plain LDS
+// read-modify-write; the caller gives the wave exclusive access).  Points of
+// the wave with the same latent in the same slot are added one at a time.
 // One workgroup of 8 waves; with statistics, one workgroup per CU holding
 // the LDS sums [A | B][HL][D] of latents < HL.
 template <int HP, int GAMMA, bool MAG, int NPIX>
@@ -329,212 +299,204 @@ __global__ __launch_bounds__(512) void k_states_maxtree(
     const int32_t* __restrict__ sel, const uint32_t* __restrict__ tab_act,
     const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
     uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk, int accum, int HL,
-    const float* __restrict__ ymax_p, int wpts, float sB, long long* __restrict__ part,
-    float* __restrict__ AT, float* __restrict__ BT, int Dq, double* __restrict__ scal) {
+    float* __restrict__ part, float* __restrict__ AT, float* __restrict__ BT, int Dq,
+    double* __restrict__ scal) {
   constexpr int NS = nstates_c(HP, GAMMA);
   constexpr int NB = (NS + 15) / 16;
-  extern __shared__ unsigned acc_lds[];  // [A | B][HL][D], fixed point
+  extern __shared__ float acc_lds[];  // [A | B][HL][D]
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, l = lane & 15;
   const float c1 = th->c1_2, lam2 = th->lam2, beta = th->beta;
   const int nacc = 2 * HL * D;
   const bool lds_acc = accum && HL > 0;
-  const float sA = accum ? maxtree_scale_a(*ymax_p, wpts) : 0.0f;
   if (lds_acc) {
-    for (int i = threadIdx.x; i < nacc; i += 512) acc_lds[i] = 0u;
+    for (int i = threadIdx.x; i < nacc; i += 512) acc_lds[i] = 0.0f;
     __syncthreads();
   }
   double acc_k = 0.0, acc_l = 0.0, acc_r = 0.0;
-  int windows = 0;
 
-  // the sweep count is uniform over the workgroup (the window barriers)
-  for (int64_t sweep = (int64_t)blockIdx.x * 32, k = 0; sweep < N;
-       sweep += (int64_t)gridDim.x * 32, ++k) {
-    if (lds_acc && k > 0 && k % MAXTREE_WIN_SWEEPS == 0) {
-      maxtree_flush(acc_lds, nacc, part + (int64_t)blockIdx.x * nacc, windows > 0);
-      ++windows;
-    }
+  for (int64_t sweep = (int64_t)blockIdx.x * 32; sweep < N; sweep += (int64_t)gridDim.x * 32) {
     const int64_t base = sweep + wave * 4;
-    if (base >= N) continue;  // past the end: nothing for this wave in the sweep
+    if (base >= N) break;  // past the end (later sweeps only go further)
     const int64_t n = base + g;
     const bool valid = n < N;
     const int64_t nn = valid ? n : N - 1;
     float y[NPIX];
-    float P[HP][NPIX];
+    int hsel[HP];
+    Pass2<HP, NPIX, NB> p2;
     {
-      int hsel[HP];
+      float P[HP][NPIX];
+      {
 #pragma unroll
-      for (int j = 0; j < HP; ++j) hsel[j] = sel[nn * HP + j];
+        for (int j = 0; j < HP; ++j) hsel[j] = sel[nn * HP + j];
 #pragma unroll
-      for (int i = 0; i < NPIX; ++i) {
-        const int d = l + 16 * i;
-        y[i] = d < D ? Y[nn * D + d] : 0.0f;
-      }
-      // rows of P are zero beyond D and at least 16 NPIX long
-#pragma unroll
-      for (int j = 0; j < HP; ++j)
-#pragma unroll
-        for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
-    }
-
-    // ---- pass 1: log-joints (log2 units) and residuals of every state
-    Pass1<HP, GAMMA, MAG, NPIX> p1(y, l, c1, lam2);
-    {
-      float zero[NPIX];
-#pragma unroll
-      for (int i = 0; i < NPIX; ++i) zero[i] = 0.0f;
-      p1.template leaf<0u>(zero);
-      static_for<1, GAMMA + 1>([&](auto kc) {
-        constexpr int K = decltype(kc)::value;
-        // fresh identities for P per cardinality (no instruction): value
-        // numbering would otherwise share the prefixes of one cardinality
-        // with the next and keep them all live in between
+        for (int i = 0; i < NPIX; ++i) {
+          const int d = l + 16 * i;
+          y[i] = d < D ? Y[nn * D + d] : 0.0f;
+        }
+        // rows of P are zero beyond D and at least 16 NPIX long
 #pragma unroll
         for (int j = 0; j < HP; ++j)
 #pragma unroll
-          for (int i = 0; i < NPIX; ++i) asm volatile("" : "+v"(P[j][i]));
-        Enum<HP, NPIX, MAG, K, 0, -1, 0u>::run(P, zero, p1);
-      });
-    }
-    const float m = row_max16(p1.mx);
-    float z = 0.0f, z1 = 0.0f;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float dd = p1.lj[b] - m;  // -inf for the padding entries
-      z1 += __builtin_amdgcn_exp2f(dd);
-      z += beta == 1.0f ? __builtin_amdgcn_exp2f(dd) : __builtin_amdgcn_exp2f(beta * dd);
-    }
-    const float Z = row_sum16(z);
-    const float Z1 = beta == 1.0f ? Z : row_sum16(z1);
-    const float invZ = 1.0f / Z;
-
-    // ---- top-k: repeated arg-max below the previous winner in (lj desc, index asc)
-    if (topk > 0) {
-      float pv = INFINITY;
-      int pid = -1;
-      for (int t = 0; t < topk; ++t) {
-        float v = -INFINITY;
-        int id = 0x7fffffff;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const int k = 16 * b + l;
-          const float x = p1.lj[b];
-          const bool below = (x < pv) || (x == pv && k > pid);
-          if (k < NS && below && (x > v || id == 0x7fffffff)) {
-            v = x;
-            id = k;
-          }
-        }
-        argmax_step<DPP_MIRROR>(v, id);
-        argmax_step<DPP_HALF_MIRROR>(v, id);
-        argmax_step<DPP_XOR2>(v, id);
-        argmax_step<DPP_XOR1>(v, id);
-        if (l == 0 && valid) {
-          if (top_q) top_q[n * topk + t] = __builtin_amdgcn_exp2f(beta * (v - m)) * invZ;
-          if (top_mask) top_mask[n * topk + t] = tab_act[id];
-        }
-        pv = v;
-        pid = id;
+          for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
       }
-    }
 
-    // ---- q, moments, expected residual
-    Pass2<HP, NPIX, NB> p2;
-    float res = 0.0f;
-    float sm[HP];
+      // ---- pass 1: log-joints (log2 units) and residuals of every state
+      Pass1<HP, GAMMA, MAG, NPIX> p1(y, l, c1, lam2);
+      {
+        float zero[NPIX];
 #pragma unroll
-    for (int j = 0; j < HP; ++j) sm[j] = 0.0f;
+        for (int i = 0; i < NPIX; ++i) zero[i] = 0.0f;
+        p1.template leaf<0u>(zero);
+        static_for<1, GAMMA + 1>([&](auto kc) {
+          constexpr int K = decltype(kc)::value;
+          // fresh identities for P per cardinality (no instruction): value
+          // numbering would otherwise share the prefixes of one cardinality
+          // with the next and keep them all live in between
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int t = 16 * b + l;
-      const float qv = __builtin_amdgcn_exp2f(beta * (p1.lj[b] - m)) * invZ;  // 0 on padding
-      res = __builtin_fmaf(qv, p1.rs[b], res);
-      const uint32_t act = t < NS ? tab_act[t] : 0u;
+          for (int j = 0; j < HP; ++j)
 #pragma unroll
-      for (int j = 0; j < HP; ++j) sm[j] += ((act >> j) & 1u) ? qv : 0.0f;
-      p2.q[b] = qv;
-    }
-    float kmean = 0.0f;
+            for (int i = 0; i < NPIX; ++i) asm volatile("" : "+v"(P[j][i]));
+          Enum<HP, NPIX, MAG, K, 0, -1, 0u>::run(P, zero, p1);
+        });
+      }
+      const float m = row_max16(p1.mx);
+      float z = 0.0f, z1 = 0.0f;
 #pragma unroll
-    for (int j = 0; j < HP; ++j) {
-      sm[j] = row_sum16(sm[j]);
-      kmean += sm[j];
-    }
-    if (valid) {
-#pragma unroll
-      for (int j = 0; j < HP; ++j)
-        if (l == j) s_mean[n * HP + j] = sm[j];
-    }
-    const float resid = row_sum16(res);  // <||y - f(s)||^2>, relative to ||y||^2 for MMCA
-    double yy_n = 0.0;  // ||y||^2 in FP64 (MMCA: added back to logL and the residual)
-    if constexpr (MAG) {
-#pragma unroll
-      for (int i = 0; i < NPIX; ++i) yy_n += (double)y[i] * (double)y[i];
-#pragma unroll
-      for (int o = 8; o >= 1; o >>= 1) yy_n += __shfl_xor(yy_n, o, 64);
-    }
-    const double lL = th->c0 + 0.6931471805599453 * ((double)m + (double)log2f(Z1) -
-                                                     (double)lam2 * yy_n);
-    if (l == 0 && valid) {
-      if (logL) logL[n] = (float)lL;
-      acc_k += kmean;
-      acc_l += lL;
-      acc_r += (double)resid + yy_n;
-    }
+      for (int b = 0; b < NB; ++b) {
+        const float dd = p1.lj[b] - m;  // -inf for the padding entries
+        z1 += __builtin_amdgcn_exp2f(dd);
+        z += beta == 1.0f ? __builtin_amdgcn_exp2f(dd) : __builtin_amdgcn_exp2f(beta * dd);
+      }
+      const float Z = row_sum16(z);
+      const float Z1 = beta == 1.0f ? Z : row_sum16(z1);
+      const float invZ = 1.0f / Z;
 
-    // ---- pass 2: responsibilities
-    if (accum) {
-      // P read again (from L2): nothing of pass 1 stays live across the
-      // log-sum-exp, and value numbering cannot carry pass 1's maxima over
-      // to the equal ones here
-      int hsel[HP];
+      // ---- top-k: repeated arg-max below the previous winner in (lj desc, index asc)
+      if (topk > 0) {
+        float pv = INFINITY;
+        int pid = -1;
+        for (int t = 0; t < topk; ++t) {
+          float v = -INFINITY;
+          int id = 0x7fffffff;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int k = 16 * b + l;
+            const float x = p1.lj[b];
+            const bool below = (x < pv) || (x == pv && k > pid);
+            if (k < NS && below && (x > v || id == 0x7fffffff)) {
+              v = x;
+              id = k;
+            }
+          }
+          argmax_step<DPP_MIRROR>(v, id);
+          argmax_step<DPP_HALF_MIRROR>(v, id);
+          argmax_step<DPP_XOR2>(v, id);
+          argmax_step<DPP_XOR1>(v, id);
+          if (l == 0 && valid) {
+            if (top_q) top_q[n * topk + t] = __builtin_amdgcn_exp2f(beta * (v - m)) * invZ;
+            if (top_mask) top_mask[n * topk + t] = tab_act[id];
+          }
+          pv = v;
+          pid = id;
+        }
+      }
+
+      // ---- q, moments, expected residual
+      float res = 0.0f;
+      float sm[HP];
+#pragma unroll
+      for (int j = 0; j < HP; ++j) sm[j] = 0.0f;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int t = 16 * b + l;
+        const float qv = __builtin_amdgcn_exp2f(beta * (p1.lj[b] - m)) * invZ;  // 0 on padding
+        res = __builtin_fmaf(qv, p1.rs[b], res);
+        const uint32_t act = t < NS ? tab_act[t] : 0u;
+#pragma unroll
+        for (int j = 0; j < HP; ++j) sm[j] += ((act >> j) & 1u) ? qv : 0.0f;
+        p2.q[b] = qv;
+      }
+      float kmean = 0.0f;
 #pragma unroll
       for (int j = 0; j < HP; ++j) {
-        hsel[j] = sel[nn * HP + j];
-#pragma unroll
-        for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
+        sm[j] = row_sum16(sm[j]);
+        kmean += sm[j];
       }
-      // 2^-40 of the largest weight of this point (1/Z: the best state's)
-      p2.thr = valid ? 0x1p-40f * invZ : INFINITY;
-#pragma unroll
-      for (int j = 0; j < HP; ++j)
-#pragma unroll
-        for (int i = 0; i < NPIX; ++i) p2.R[j][i] = 0.0f;
-      float b0[NPIX], U0[NPIX];
-#pragma unroll
-      for (int i = 0; i < NPIX; ++i) {
-        b0[i] = 0.0f;
-        U0[i] = 0.0f;
-      }
-      Resp<HP, GAMMA, NPIX, MAG, 0, -1, 0u>::run(P, b0, U0, p2);
       if (valid) {
 #pragma unroll
+        for (int j = 0; j < HP; ++j)
+          if (l == j) s_mean[n * HP + j] = sm[j];
+      }
+      const float resid = row_sum16(res);  // <||y - f(s)||^2>, relative to ||y||^2 for MMCA
+      double yy_n = 0.0;  // ||y||^2 in FP64 (MMCA: added back to logL and the residual)
+      if constexpr (MAG) {
+#pragma unroll
+        for (int i = 0; i < NPIX; ++i) yy_n += (double)y[i] * (double)y[i];
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) yy_n += __shfl_xor(yy_n, o, 64);
+      }
+      const double lL = th->c0 + 0.6931471805599453 * ((double)m + (double)log2f(Z1) -
+                                                       (double)lam2 * yy_n);
+      if (l == 0 && valid) {
+        if (logL) logL[n] = (float)lL;
+        acc_k += kmean;
+        acc_l += lL;
+        acc_r += (double)resid + yy_n;
+      }
+
+      // ---- pass 2: responsibilities
+      if (accum) {
+        // P read again (from L2): nothing of pass 1 stays live across the
+        // log-sum-exp, and value numbering cannot carry pass 1's maxima over
+        // to the equal ones here
+#pragma unroll
         for (int j = 0; j < HP; ++j) {
-          const int h = hsel[j];
-          if (h < HL) {
-            unsigned* la = acc_lds + h * D;
-            unsigned* lb = acc_lds + (HL + h) * D;
+          hsel[j] = sel[nn * HP + j];
 #pragma unroll
-            for (int i = 0; i < NPIX; ++i) {
-              const int d = l + 16 * i;
-              const float r = p2.R[j][i];
-              if (d < D && r != 0.0f) {
-                // two's complement: the int32 sum is the wrapped u32 sum
-                atomicAdd(la + d, (unsigned)__float2int_rn(r * y[i] * sA));
-                atomicAdd(lb + d, __float2uint_rn(r * sB));
+          for (int i = 0; i < NPIX; ++i) P[j][i] = Pt32[(int64_t)hsel[j] * Dp + l + 16 * i];
+        }
+        // 2^-40 of the largest weight of this point (1/Z: the best state's)
+        p2.thr = valid ? 0x1p-40f * invZ : INFINITY;
+#pragma unroll
+        for (int j = 0; j < HP; ++j)
+#pragma unroll
+          for (int i = 0; i < NPIX; ++i) p2.R[j][i] = 0.0f;
+        float b0[NPIX], U0[NPIX];
+#pragma unroll
+        for (int i = 0; i < NPIX; ++i) {
+          b0[i] = 0.0f;
+          U0[i] = 0.0f;
+        }
+        Resp<HP, GAMMA, NPIX, MAG, 0, -1, 0u>::run(P, b0, U0, p2);
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < HP; ++j) {
+            const int h = hsel[j];
+            if (h < HL) {
+              float* la = acc_lds + h * D;
+              float* lb = acc_lds + (HL + h) * D;
+#pragma unroll
+              for (int i = 0; i < NPIX; ++i) {
+                const int d = l + 16 * i;
+                const float r = p2.R[j][i];
+                if (d < D && r != 0.0f) {
+                  atomicAdd(la + d, r * y[i]);
+                  atomicAdd(lb + d, r);
+                }
               }
-            }
-          } else {
-            float* at = AT + (int64_t)(h - HL) * Dq;
-            float* bt = BT + (int64_t)(h - HL) * Dq;
+            } else {
+              float* at = AT + (int64_t)(h - HL) * Dq;
+              float* bt = BT + (int64_t)(h - HL) * Dq;
 #pragma unroll
-            for (int i = 0; i < NPIX; ++i) {
-              const int d = l + 16 * i;
-              const float r = p2.R[j][i];
-              if (d < D && r != 0.0f) {
-                atomicAdd(at + d, r * y[i]);
-                atomicAdd(bt + d, r);
+              for (int i = 0; i < NPIX; ++i) {
+                const int d = l + 16 * i;
+                const float r = p2.R[j][i];
+                if (d < D && r != 0.0f) {
+                  atomicAdd(at + d, r * y[i]);
+                  atomicAdd(bt + d, r);
+                }
               }
             }
           }
@@ -547,53 +509,44 @@ __global__ __launch_bounds__(512) void k_states_maxtree(
     atomicAdd(&scal[1], acc_l);
     atomicAdd(&scal[3], acc_r);
   }
-  if (lds_acc) maxtree_flush(acc_lds, nacc, part + (int64_t)blockIdx.x * nacc, windows > 0);
+  if (lds_acc) {
+    __syncthreads();
+    float* dst = part + (int64_t)blockIdx.x * nacc;
+    for (int i = threadIdx.x; i < nacc; i += 512) dst[i] = acc_lds[i];
+  }
 }
 
-// A[d][h] += sum over workgroups of the partials (latents < HL), scaled back.
+// A[d][h] += sum over workgroups of their sums (latents < HL), added in FP64.
 // Each block takes 64 entries; its four waves sum a quarter of the
-// workgroup partials each.
-__global__ __launch_bounds__(256) void k_reduce_parts(const long long* __restrict__ part,
-                                                      int nparts, int HL, int D, int H,
-                                                      const float* __restrict__ ymax_p, int wpts,
-                                                      float sB, float* __restrict__ A,
+// workgroup sums each.
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int nparts,
+                                                      int HL, int D, int H,
+                                                      float* __restrict__ A,
                                                       float* __restrict__ B) {
-  __shared__ long long red[4][64];
+  __shared__ double red[4][64];
   const int nacc = 2 * HL * D;
   const int e = blockIdx.x * 64 + (threadIdx.x & 63);
   const int q = threadIdx.x >> 6;
-  long long s0 = 0, s1 = 0;
+  double s0 = 0.0, s1 = 0.0;
   if (e < nacc) {
     int w = q;
     for (; w + 4 < nparts; w += 8) {
-      s0 += part[(int64_t)w * nacc + e];
-      s1 += part[(int64_t)(w + 4) * nacc + e];
+      s0 += (double)part[(int64_t)w * nacc + e];
+      s1 += (double)part[(int64_t)(w + 4) * nacc + e];
     }
-    if (w < nparts) s0 += part[(int64_t)w * nacc + e];
+    if (w < nparts) s0 += (double)part[(int64_t)w * nacc + e];
   }
   red[q][threadIdx.x & 63] = s0 + s1;
   __syncthreads();
   if (q == 0 && e < nacc) {
-    const long long tot = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                          red[3][threadIdx.x];
+    const double tot = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                       red[3][threadIdx.x];
     const int which = e / (HL * D);
     const int r = e - which * HL * D;
     const int h = r / D, d = r - h * D;
-    const double inv = which ? 1.0 / (double)sB : 1.0 / (double)maxtree_scale_a(*ymax_p, wpts);
     float* dst = which ? B : A;
-    dst[(int64_t)d * H + h] += (float)((double)tot * inv);
+    dst[(int64_t)d * H + h] += (float)tot;
   }
-}
-
-// max |y| over the batch into *ymax (cleared beforehand), as the order-
-// preserving bit pattern of a non-negative float.
-__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ Y, int64_t n,
-                                                float* __restrict__ ymax) {
-  float m = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, fabsf(Y[i]));
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned*>(ymax), __float_as_uint(m));
 }
 
 // Fill of the transposed accumulators (a kernel, so that the call can be
@@ -656,26 +609,26 @@ static int maxtree_hl(int D, int H) {
   return hl < H ? hl : H;
 }
 
-// Scratch of the statistics (in floats): ymax (64), the int64 workgroup
-// partials, the transposed float sums of the latents beyond LDS.
+// Scratch of the statistics (in floats): the workgroup sums, then the
+// transposed sums of the latents beyond LDS.
 size_t max_tree_acc_floats(int D, int H, int nparts) {
   const int HL = maxtree_hl(D, H);
-  return 64 + (size_t)nparts * 2 * HL * D * 2 + 2 * (size_t)(H - HL) * round_up(D, 16);
+  return (size_t)nparts * 2 * HL * D + 2 * (size_t)(H - HL) * round_up(D, 16);
 }
 
 template <int HP, int GAMMA, bool MAG, int NPIX>
 static hipError_t launch_mt(const float* Y, int64_t N, int D, int Dp, const Prepared& p,
                             const Scratch& s, const uint32_t* tab_act, float* logL,
                             uint32_t* top_mask, float* top_q, int topk, int accum, int HL,
-                            int blocks, const float* ymax, int wpts, float sB, long long* part,
-                            float* AT, float* BT, int Dq, double* scal, hipStream_t st) {
+                            int blocks, float* part, float* AT, float* BT, int Dq,
+                            double* scal, hipStream_t st) {
   auto kern = k_states_maxtree<HP, GAMMA, MAG, NPIX>;
   const size_t lds = accum ? (size_t)2 * HL * D * 4 : 0;
   hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
   if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(512), lds, st, Y, N, D, Dp, p.Pt32,
                      s.sel, tab_act, p.theta, s.s_mean, logL, top_mask, top_q, topk, accum, HL,
-                     ymax, wpts, sB, part, AT, BT, Dq, scal);
+                     part, AT, BT, Dq, scal);
   return hipGetLastError();
 }
 
@@ -690,45 +643,30 @@ hipError_t launch_states_max_tree(int model, int Hp, int gamma, int64_t N, int D
   const int Dq = round_up(D, 16);
   const int64_t groups = (N + 31) / 32;  // 32 points per workgroup and sweep
   const int accum = A_num != nullptr ? 1 : 0;
-  int HL = 0, blocks, wpts = 32;
-  float sB = 0.0f;
-  float *ymax = nullptr, *AT = nullptr, *BT = nullptr;
-  long long* part = nullptr;
+  int HL = 0, blocks;
+  float *part = nullptr, *AT = nullptr, *BT = nullptr;
   if (accum) {
     if (!s.max_acc || s.max_parts <= 0) return hipErrorInvalidValue;
     HL = maxtree_hl(D, H);
     blocks = (int)(groups < s.max_parts ? groups : s.max_parts);
-    const int64_t sweeps = (groups + blocks - 1) / blocks;  // per workgroup
-    wpts = 32 * (int)(sweeps < MAXTREE_WIN_SWEEPS ? sweeps : MAXTREE_WIN_SWEEPS);
-    sB = maxtree_scale_b(wpts);
-    ymax = s.max_acc;
-    part = reinterpret_cast<long long*>(s.max_acc + 64);
-    AT = s.max_acc + 64 + (size_t)s.max_parts * 2 * HL * D * 2;
+    part = s.max_acc;
+    AT = part + (size_t)s.max_parts * 2 * HL * D;
     BT = AT + (size_t)(H - HL) * Dq;
-    // clear ymax and the float sums in one fill (they are contiguous but for
-    // the partials, which every workgroup stores before it adds)
-    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, st, ymax, (int64_t)64);
     if (H > HL) {
       const int64_t nf = 2 * (int64_t)(H - HL) * Dq;
       const int64_t fb = (nf + 255) / 256;
       hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(fb < 1024 ? fb : 1024)), dim3(256), 0,
                          st, AT, nf);
     }
-    const int64_t ny = N * (int64_t)D;
-    const int64_t yb = (ny + 255) / 256;
-    hipLaunchKernelGGL(k_absmax, dim3((unsigned)(yb < 2048 ? yb : 2048)), dim3(256), 0, st, Y,
-                       ny, ymax);
   } else {
     blocks = (int)(groups < 2048 ? groups : 2048);
   }
   hipError_t e = hipErrorInvalidValue;
 #define LAUNCH(HPV, GV, NP)                                                                    \
   (mag ? launch_mt<HPV, GV, true, NP>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q, topk, \
-                                      accum, HL, blocks, ymax, wpts, sB, part, AT, BT, Dq,     \
-                                      scal, st)                                                \
+                                      accum, HL, blocks, part, AT, BT, Dq, scal, st)           \
        : launch_mt<HPV, GV, false, NP>(Y, N, D, Dp, p, s, tab_act, logL, top_mask, top_q,      \
-                                       topk, accum, HL, blocks, ymax, wpts, sB, part, AT, BT,  \
-                                       Dq, scal, st))
+                                       topk, accum, HL, blocks, part, AT, BT, Dq, scal, st))
 #define X(HPV, GV)                       \
   if (Hp == HPV && gamma == GV) {        \
     if (npix == 4)                       \
@@ -745,7 +683,7 @@ hipError_t launch_states_max_tree(int model, int Hp, int gamma, int64_t N, int D
   if (HL > 0) {
     const int nacc = 2 * HL * D;
     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((nacc + 63) / 64)), dim3(256), 0, st,
-                       part, blocks, HL, D, H, ymax, wpts, sB, A_num, B_den);
+                       part, blocks, HL, D, H, A_num, B_den);
   }
   if (H > HL) {
     dim3 grid((unsigned)((H - HL + 31) / 32), (unsigned)((D + 31) / 32));

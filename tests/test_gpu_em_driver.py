@@ -1,0 +1,84 @@
+"""The EM driver objects of the user interface on the GPU: each annealed EM
+iteration of `EM(model, anneal).run()` against one oracle EM step (E-step at
+the schedule's temperature, then the M-step) from the parameters the GPU run
+held before it, and `model.inference` against the oracle's top states."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import prosper_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("name,N,Hp,gamma,cls", [("bars", 300, 10, 10, "BSC_ET"),
+                                                 ("tsc", 300, 8, 3, "TSC_ET"),
+                                                 ("mca", 200, 10, 3, "MCA_ET")])
+def test_annealed_em_iterations_match_oracle_steps(name, N, Hp, gamma, cls):
+    import torch
+    from paper_1908_06843_amd import em
+    Y, _, _, wl = synth.make_workload(name, N=N)
+    model = getattr(em, cls)(wl.D, wl.H, Hp, gamma, precision="fp32", device=0)
+    params = model.standard_init({"y": Y}, seed=3)
+    anneal = em.LinearAnnealing(3, beta_start=0.5)
+    hist = [(params["W"].cpu().numpy().astype(np.float64), params["pi"], params["sigma"])]
+
+    def keep(it, W, theta):
+        th = theta.cpu().numpy()
+        hist.append((W.cpu().numpy().astype(np.float64), float(th[0]), float(th[1])))
+
+    run = em.EM(model, anneal, data={"y": Y}, lparams=params)
+    out = run.run(callback=keep)
+    assert len(hist) == 4 and len(run.logL) == 3
+    for it in range(3):
+        W, pi, sigma = hist[it]
+        beta = anneal.beta(it)
+        r = O.estep(wl.model, Y, W, pi, sigma, Hp, gamma, beta=beta,
+                    keep_posterior=(wl.model != "mca"))
+        Wr, pir, sr = O.mstep(wl.model, Y, W, r)
+        Wg, pig, sg = hist[it + 1]
+        print(f"[em] {name} it={it} beta={beta}: W {rel(Wg, Wr):.2e} pi {pig} vs {pir} "
+              f"sigma {sg} vs {sr} logL {run.logL[it]} vs {r['scal'][1]}", flush=True)
+        # one FP32 E-step's statistics (2e-5) through the FP64 solve
+        assert rel(Wg, Wr) < 1e-4
+        assert pig == pytest.approx(pir, rel=1e-5)
+        assert sg == pytest.approx(sr, rel=1e-5)
+        assert run.logL[it] == pytest.approx(r["scal"][1], rel=1e-5)
+    np.testing.assert_array_equal(out["W"].cpu().numpy(), hist[-1][0].astype(np.float32))
+
+
+@pytest.mark.parametrize("name,N,Hp,gamma,cls", [("bsc256", 200, 12, 4, "BSC_ET"),
+                                                 ("tsc", 200, 8, 3, "TSC_ET")])
+def test_inference_top_states(name, N, Hp, gamma, cls):
+    from paper_1908_06843_amd import em
+    Y, Wgt, _, wl = synth.make_workload(name, N=N)
+    model = getattr(em, cls)(wl.D, wl.H, Hp, gamma, precision="fp32", device=0)
+    params = {"W": Wgt.astype(np.float32), "pi": wl.pi, "sigma": wl.sigma}
+    res = model.inference(em.LinearAnnealing(1), params, Y, topk=3)
+    s, p = res["s"].cpu().numpy(), res["p"].cpu().numpy()
+    assert s.shape == (N, 3, wl.H) and p.shape == (N, 3)
+    r = O.estep(wl.model, Y, Wgt, wl.pi, wl.sigma, Hp, gamma, topk=3)
+    act, sgn = O.state_masks(wl.model, Hp, gamma)
+    checked = 0
+    for n in range(N):
+        if r["flagged"][n] or not np.array_equal(res["sel"][n].cpu().numpy(), r["sel"][n]):
+            continue
+        pt = O.estep_point(wl.model, Y[n], Wgt, wl.pi, wl.sigma, Hp, gamma)
+        for t in range(3):
+            # the state the GPU returns carries the oracle probability of rank t
+            vec = s[n, t]
+            assert np.all(vec[np.setdiff1d(np.arange(wl.H), r["sel"][n])] == 0)
+            sub = vec[r["sel"][n]]
+            a = int(sum(1 << j for j in range(Hp) if sub[j] != 0))
+            g = int(sum(1 << j for j in range(Hp) if sub[j] < 0))
+            idx = [i for i in range(len(act)) if act[i] == a and (wl.model != "tsc" or sgn[i] == g)]
+            assert len(idx) == 1
+            q_ref = r["top_q"][n, t]
+            assert abs(pt["q"][idx[0]] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
+            assert abs(p[n, t] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
+        checked += 1
+    assert checked > 0.9 * N
