@@ -203,13 +203,15 @@ def serving_bench(np, api, n_req, prec):
     def poisson(frac):
         gaps = g.exponential(1.0 / (frac * sat_rate), len(reqs))
         lat = [0.0] * len(reqs)
+        stages = [None] * len(reqs)
         ids2 = [None] * len(reqs)
 
         def waiter():
             for i in range(len(reqs)):
                 while ids2[i] is None:
                     time.sleep(5e-5)
-                lat[i] = srv.wait(ids2[i])
+                stages[i] = srv.wait_stages(ids2[i])
+                lat[i] = stages[i]["total"]
 
         th = threading.Thread(target=waiter)
         th.start()
@@ -223,8 +225,18 @@ def serving_bench(np, api, n_req, prec):
         th.join()
         load_s = time.perf_counter() - t0
         lat = np.array(lat)
-        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "patches_per_s": patches / load_s}
+        p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+        # where the time of the slowest 1% goes, beside that of the middle band
+        tail = [st for st, l in zip(stages, lat) if l >= p99]
+        mid = [st for st, l in zip(stages, lat)
+               if np.percentile(lat, 40) <= l <= np.percentile(lat, 60)]
+
+        def mean_stages(group):
+            return {k: float(np.mean([st[k] for st in group])) for k in srv.STAGES} if group else None
+        return {"p50_ms": float(p50), "p99_ms": float(p99), "patches_per_s": patches / load_s,
+                "stages_ms_p99_tail": mean_stages(tail), "stages_ms_median_band": mean_stages(mid),
+                "tail_patches_mean": float(np.mean([reqs[i][0].shape[0] for i in range(len(reqs))
+                                                    if lat[i] >= p99]))}
 
     at = {f"{f}x": poisson(f) for f in (0.5, 0.8, 0.95)}
     srv.stop()

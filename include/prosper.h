@@ -223,19 +223,29 @@ prosper_status prosper_estep_static(const prosper_args* args, const float* Y, co
 
 /* M-step ----------------------------------------------------------------- */
 
-/* New parameters from one E-step's statistics, in FP64 on the device.
+/* The M-step of truncated EM (section "Learning Algorithm and Data Models":
+ * the parameters that maximise the free energy under the truncated
+ * posteriors of the E-step, for the data models of Table 1): new parameters
+ * from one E-step's statistics, in FP64 on the device.
  *   BSC/TSC: W_new = A B^-1 on the latents with B_hh > 0 (Cholesky of that
  *            block; other columns keep W_old), pi = scal[0]/(N H),
  *            sigma^2 = (scal[2] - 2 tr(W_new^T A) + tr(W_new^T W_new B))/(N D)
  *   MCA:     W_new[d,h] = A[d,h]/B[d,h] where B[d,h] > 0 (else W_old),
  *            pi as above, sigma^2 = scal[3]/(N D)
  * W_old and W_new (D x H FP32) may alias.  theta_new (device, 2 doubles) gets
- * {pi, sigma}; it may equal args->theta_dev.  args supplies model, D, H. */
+ * {pi, sigma}; it may equal args->theta_dev.  args supplies model, D, H.
+ * Errors: EINVAL for a NULL pointer, an unknown model or D, H out of range;
+ * EDEVICE for a HIP failure (message in prosper_last_error). */
 prosper_status prosper_mstep(prosper_ctx* ctx, const prosper_args* args,
                              const prosper_acc* acc, const float* W_old, float* W_new,
                              double* theta_new, void* stream);
 
-/* Serving: E-step-only posterior inference with continuous batching ------ */
+/* Serving: E-step-only posterior inference with continuous batching ------
+ * The `inference` method of the user-interface section: for each data point
+ * of a request, the most likely latent states of its truncated posterior and
+ * their probabilities (top_mask / top_q), with the preselection, posterior
+ * means and logL of prosper_point_out, for a dictionary the server keeps
+ * resident. */
 
 typedef struct prosper_server prosper_server;
 
@@ -271,6 +281,15 @@ prosper_status prosper_serve_submit(prosper_server* srv, const float* Y_host, in
  * does not stop the server). */
 prosper_status prosper_serve_wait(prosper_server* srv, uint64_t req_id, int64_t timeout_us,
                                   double* latency_ms);
+
+/* prosper_serve_wait with the request's time split into stages (ms), for
+ * latency analysis: stages_ms[0] queue wait (submit to the launch of its
+ * batch), [1] the launch calls of the batch, [2] launch returned to the
+ * batch's completion seen by the scheduler (stream queueing, transfers,
+ * kernels, polling), [3] of that the GPU time of the batch (its events),
+ * [4] delivery (outputs copied to the caller, waiter woken), [5] total. */
+prosper_status prosper_serve_wait_stages(prosper_server* srv, uint64_t req_id,
+                                         int64_t timeout_us, double* stages_ms);
 
 /* Drain the queue, stop the scheduler thread and free the server. */
 prosper_status prosper_serve_stop(prosper_server* srv);

@@ -52,7 +52,8 @@ EXPORTS = [
     "prosper_ctx_create", "prosper_ctx_destroy", "prosper_last_error",
     "prosper_validate_args", "prosper_state_count", "prosper_state_table",
     "prosper_estep", "prosper_mstep", "prosper_serve", "prosper_serve_submit",
-    "prosper_serve_wait", "prosper_serve_stop", "prosper_profile", "prosper_profile_read",
+    "prosper_serve_wait", "prosper_serve_wait_stages", "prosper_serve_stop",
+    "prosper_profile", "prosper_profile_read",
     "prosper_estep_static",
 ]
 
@@ -97,6 +98,8 @@ def load() -> C.CDLL:
     lib.prosper_serve_submit.restype = i32
     lib.prosper_serve_wait.argtypes = [vp, C.c_uint64, i64, C.POINTER(dbl)]
     lib.prosper_serve_wait.restype = i32
+    lib.prosper_serve_wait_stages.argtypes = [vp, C.c_uint64, i64, C.POINTER(dbl)]
+    lib.prosper_serve_wait_stages.restype = i32
     lib.prosper_serve_stop.argtypes = [vp]
     lib.prosper_serve_stop.restype = i32
     lib.prosper_profile.argtypes = [vp, i32]

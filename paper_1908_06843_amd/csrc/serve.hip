@@ -82,7 +82,10 @@ struct Req {
   int64_t n;
   int Hp, gamma, topk;
   prosper_point_out out;
-  Clock::time_point t_submit, t_done;
+  // stage times: submit, batch launch begins / returns, completion seen by
+  // the scheduler, outputs delivered; GPU time of its batch (events)
+  Clock::time_point t_submit, t_launch, t_launched, t_seen, t_done;
+  float gpu_ms = 0.0f;
   prosper_status status = PROSPER_OK;
   bool done = false;
   int64_t row0 = 0;  // first row inside its batch
@@ -97,7 +100,8 @@ struct Batch {
   int64_t n = 0;
   size_t off = 0, bytes = 0;
   int stream = -1;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;        // end of the batch's work on its stream
+  hipEvent_t ev_start = nullptr;  // start of it
   prosper_status status = PROSPER_OK;
   bool w_sel = false, w_sm = false, w_logL = false, w_flag = false, w_tm = false, w_tq = false;
   // layout inside the pool piece
@@ -272,13 +276,26 @@ void launch(prosper_server* s, Batch* b) {
   b->stream = best;
   s->stream_load[best]++;
   hipStream_t stm = s->streams[best];
+  // timing events of the batch (a pool of them is kept; default flags, so
+  // that the batch's GPU time can be read)
+  hipError_t e = hipSuccess;
+  for (hipEvent_t* evp : {&b->ev_start, &b->ev}) {
+    if (e != hipSuccess) break;
+    if (!s->ev_pool.empty()) {
+      *evp = s->ev_pool.back();
+      s->ev_pool.pop_back();
+    } else {
+      e = hipEventCreate(evp);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->ev_start, stm);
   char* dev = s->dev_pool + b->off;
   char* pin = s->pin_pool + b->off;
   const size_t row_bytes = (size_t)s->D * 4;
-  hipError_t e = hipSuccess;
   bool all_staged = true;
   for (Req* r : b->reqs) all_staged &= r->staged;
-  if (all_staged) {
+  if (e != hipSuccess) {
+  } else if (all_staged) {
     // inputs were copied to pinned memory by the submitting threads
     for (Req* r : b->reqs)
       if (e == hipSuccess)
@@ -317,14 +334,6 @@ void launch(prosper_server* s, Batch* b) {
   if (e == hipSuccess && (b->w_sel || b->w_sm || b->w_logL || b->w_flag || b->w_tm || b->w_tq))
     e = hipMemcpyAsync(pin + b->o_sel, dev + b->o_sel, b->o_end - b->o_sel,
                        hipMemcpyDeviceToHost, stm);
-  if (e == hipSuccess) {
-    if (!s->ev_pool.empty()) {
-      b->ev = s->ev_pool.back();
-      s->ev_pool.pop_back();
-    } else {
-      e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
-    }
-  }
   if (e == hipSuccess) e = hipEventRecord(b->ev, stm);
   if (e != hipSuccess) {
     s->err = std::string("serve launch: ") + hipGetErrorString(e);
@@ -351,7 +360,8 @@ void deliver(prosper_server* s, Batch* b) {
     if (r->out.top_q && K) std::memcpy(r->out.top_q, pin + b->o_tq + r0 * K * 4, n * K * 4);
   }
   if (b->ev) s->ev_pool.push_back(b->ev);
-  b->ev = nullptr;
+  if (b->ev_start) s->ev_pool.push_back(b->ev_start);
+  b->ev = b->ev_start = nullptr;
   if (b->stream >= 0) s->stream_load[b->stream]--;
   s->pool.release(b->off, b->bytes);
 }
@@ -382,7 +392,11 @@ void scheduler(prosper_server* s) {
       }
     }
     for (Batch* b : admit) {
+      const Clock::time_point t0 = Clock::now();
+      for (Req* r : b->reqs) r->t_launch = t0;
       launch(s, b);
+      const Clock::time_point t1 = Clock::now();
+      for (Req* r : b->reqs) r->t_launched = t1;
       if (b->status != PROSPER_OK) done.push_back(b);
       else s->inflight.push_back(b);
     }
@@ -394,6 +408,14 @@ void scheduler(prosper_server* s) {
         continue;
       }
       if (q != hipSuccess) b->status = PROSPER_EDEVICE;
+      const Clock::time_point t_seen = Clock::now();
+      float gpu_ms = 0.0f;
+      if (q == hipSuccess && hipEventElapsedTime(&gpu_ms, b->ev_start, b->ev) != hipSuccess)
+        gpu_ms = 0.0f;
+      for (Req* r : b->reqs) {
+        r->t_seen = t_seen;
+        r->gpu_ms = gpu_ms;
+      }
       done.push_back(b);
       s->inflight.erase(s->inflight.begin() + i);
     }
@@ -467,6 +489,13 @@ prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_devi
     hipStream_t st;
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) s->streams.push_back(st);
+  }
+  // the batches' start and end events, made here rather than on the
+  // scheduler thread (creating one there delays every request behind it)
+  for (int i = 0; e == hipSuccess && i < 2 * max_inflight + 2; ++i) {
+    hipEvent_t ev;
+    e = hipEventCreate(&ev);
+    if (e == hipSuccess) s->ev_pool.push_back(ev);
   }
   if (e == hipSuccess) {
     s->prep = carve_prep(s->prep_mem, s->Dp, H, precision);
@@ -543,8 +572,8 @@ prosper_status prosper_serve_submit(prosper_server* s, const float* Y_host, int6
   return PROSPER_OK;
 }
 
-prosper_status prosper_serve_wait(prosper_server* s, uint64_t id, int64_t timeout_us,
-                                  double* latency_ms) {
+static prosper_status serve_wait(prosper_server* s, uint64_t id, int64_t timeout_us,
+                                 double* latency_ms, double* stages_ms) {
   if (!s) return PROSPER_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(id);
@@ -556,12 +585,33 @@ prosper_status prosper_serve_wait(prosper_server* s, uint64_t id, int64_t timeou
                                   [&] { return r->done; })) {
     return PROSPER_ETIMEDOUT;
   }
-  if (latency_ms)
-    *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  auto ms = [](Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  if (latency_ms) *latency_ms = ms(r->t_submit, r->t_done);
+  if (stages_ms) {
+    const bool ran = r->t_launch.time_since_epoch().count() != 0;
+    stages_ms[0] = ran ? ms(r->t_submit, r->t_launch) : 0.0;
+    stages_ms[1] = ran ? ms(r->t_launch, r->t_launched) : 0.0;
+    stages_ms[2] = ran ? ms(r->t_launched, r->t_seen) : 0.0;
+    stages_ms[3] = r->gpu_ms;
+    stages_ms[4] = ran ? ms(r->t_seen, r->t_done) : 0.0;
+    stages_ms[5] = ms(r->t_submit, r->t_done);
+  }
   prosper_status st = r->status;
   s->reqs.erase(it);
   delete r;
   return st;
+}
+
+prosper_status prosper_serve_wait(prosper_server* s, uint64_t id, int64_t timeout_us,
+                                  double* latency_ms) {
+  return serve_wait(s, id, timeout_us, latency_ms, nullptr);
+}
+
+prosper_status prosper_serve_wait_stages(prosper_server* s, uint64_t id, int64_t timeout_us,
+                                         double* stages_ms) {
+  return serve_wait(s, id, timeout_us, nullptr, stages_ms);
 }
 
 prosper_status prosper_serve_stop(prosper_server* s) {

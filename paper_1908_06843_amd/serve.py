@@ -90,6 +90,22 @@ class Server:
             raise _lib.ProsperError(st, f"request {rid} failed")
         return lat.value
 
+    STAGES = ("queue", "launch", "device_span", "gpu", "delivery", "total")
+
+    def wait_stages(self, rid: int, timeout_us: int = -1) -> dict:
+        """Like wait, returning the request's time split into stages (ms):
+        queue wait, the batch's launch calls, launch-to-completion-seen (of
+        which `gpu` is the batch's GPU time), delivery, total."""
+        st6 = (C.c_double * 6)()
+        st = _lib.load().prosper_serve_wait_stages(self.handle, C.c_uint64(rid),
+                                                   int(timeout_us), st6)
+        if st == -6:
+            raise TimeoutError(f"request {rid} still running")
+        self._live.pop(rid, None)
+        if st != 0:
+            raise _lib.ProsperError(st, f"request {rid} failed")
+        return dict(zip(self.STAGES, list(st6)))
+
     def stop(self):
         if getattr(self, "handle", None):
             _lib.load().prosper_serve_stop(self.handle)

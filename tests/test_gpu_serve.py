@@ -125,3 +125,69 @@ def test_admission_by_memory_and_errors():
             srv.wait(ids[0])                                # already collected
     finally:
         srv.stop()
+
+
+def _mmca_problem(N, seed=7):
+    """MMCA data: signed N(0,1) dictionary D=100, H=200, pi=3/H, sigma=0.3."""
+    g = synth.rng(seed)
+    W = g.standard_normal((100, 200))
+    S = synth.sample_binary(g, N, 200, 3.0 / 200)
+    Y = O.superposition(O.MMCA, W, S) + 0.3 * g.standard_normal((N, 100))
+    return Y.astype(np.float32), W.astype(np.float32), 3.0 / 200, 0.3
+
+
+@pytest.mark.parametrize("model,name,Hp,gamma", [("tsc", "tsc", 8, 3), ("mca", "mca", 10, 3),
+                                                 ("mmca", None, 10, 3)])
+def test_serving_other_models_match_oracle(model, name, Hp, gamma):
+    """TSC, MCA and MMCA dictionaries served: per-point outputs and the top
+    states against the oracle."""
+    from paper_1908_06843_amd.serve import Server
+    if model == "mmca":
+        Y, W, pi, sigma = _mmca_problem(90)
+    else:
+        Y, W, _, wl = synth.make_workload(name, N=90)
+        pi, sigma = wl.pi, wl.sigma
+        W = W.astype(np.float32)
+    srv = Server(W, pi, sigma, model=model, precision="fp32", mem_budget_bytes=32 << 20)
+    try:
+        rid, out = srv.submit(Y, Hp, gamma, topk=3,
+                              outputs=("sel", "s_mean", "logL", "flagged", "top_mask", "top_q"))
+        srv.wait(rid)
+    finally:
+        srv.stop()
+    r = O.estep(model, Y, W, pi, sigma, Hp, gamma, topk=3)
+    fl = r["flagged"].astype(bool)
+    same = np.all(out["sel"] == r["sel"], axis=1)
+    assert np.all(same | fl)
+    ok = same & ~fl
+    ts, tl = TOL["fp32"]
+    es = (np.abs(out["s_mean"][ok] - r["s_mean"][ok]).max(1)
+          / np.maximum(np.abs(r["s_mean"][ok]).max(1), 1e-3))
+    el = (np.abs(out["logL"][ok].astype(np.float64) - r["logL"][ok])
+          / np.maximum(np.abs(r["logL"][ok]), 1.0))
+    assert es.max() <= ts and el.max() <= tl, (es.max(), el.max())
+    # single-state probabilities: the FP32 rounding of one log-joint, about
+    # 15 roundings of |lj|; |lj| reaches ~100-200 log2 units for MCA and,
+    # relative to the zero state, lam ||y||^2 ~ 800 for MMCA
+    rq = {"mca": 1e-4, "mmca": 5e-4}.get(model, 3e-5)
+    np.testing.assert_allclose(out["top_q"][ok], r["top_q"][ok], rtol=rq, atol=1e-7)
+
+
+def test_wait_stages_add_up():
+    """The stage split of prosper_serve_wait_stages: all stages >= 0, the
+    host stages add up to the total, the batch's GPU time fits in the span
+    between its launch and the completion seen."""
+    from paper_1908_06843_amd.serve import Server
+    wl, g, W = _dictionary()
+    srv = Server(W, wl.pi, wl.sigma, precision="bf16", mem_budget_bytes=32 << 20)
+    try:
+        ids = [srv.submit(_patches(g, W, wl, n), 10, 4)[0] for n in (5, 300, 17, 2000, 1)]
+        for rid in ids:
+            st = srv.wait_stages(rid)
+            print(f"[stages] {st}", flush=True)
+            assert all(v >= 0.0 for v in st.values())
+            host = st["queue"] + st["launch"] + st["device_span"] + st["delivery"]
+            assert abs(host - st["total"]) <= 1e-3 + 1e-6 * st["total"]
+            assert 0.0 < st["gpu"] <= st["device_span"] + 0.05
+    finally:
+        srv.stop()
