@@ -39,6 +39,20 @@ Readings where the paper is silent (each listed in the design notes):
   from the old W in the same sweep; MMCA takes the same M-step with the
   responsibility given to the active latent of largest |W_dh|.
 
+DSC (discrete sparse coding, Table 1: linear superposition, Gaussian noise,
+discrete latents with a categorical prior): s_h takes one of V values
+phi_0 = 0, phi_1, ..., phi_{V-1} with probabilities pv_0 .. pv_{V-1} (the
+value set is given, the probabilities are learned).  Its functions are the
+dsc_* ones below, written out separately; with V = 2, phi = (0, 1) it is
+BSC and with V = 3, phi = (0, 1, -1), pv = (1 - pi, pi/2, pi/2) it is TSC.
+Readings: K_n as for TSC with the V - 1 non-zero values per active slot
+(|K| = sum_k C(H', k) (V - 1)^k), value codes of one support in mixed-radix
+counting order with the first active slot's digit least significant; the
+selection score of latent h is its best singleton log-joint over the
+non-zero values, in the units of the other scores (times sigma^2, up to
+h-independent terms); the M-step sets pv_v (v >= 1) to the expected share
+of latents taking phi_v.
+
 Parity pins: see tests/test_oracle_*.py (brute force over all states with
 scipy's multivariate normal, closed forms at H = 1, MCA == BSC special cases,
 posterior invariants, textbook least squares, the MCA update as a cluster
@@ -51,6 +65,7 @@ its W update and everything else here is pinned.
 """
 from __future__ import annotations
 
+import math
 from itertools import combinations
 from typing import Dict, List, Sequence, Tuple
 
@@ -61,7 +76,8 @@ __all__ = [
     "BSC", "TSC", "MCA", "MMCA", "MODELS", "MAX_MODELS", "TIE_REL",
     "state_table", "state_masks", "log_prior", "superposition", "log_joint",
     "selection_scores", "preselect", "estep_point", "estep", "mstep",
-    "em_run", "free_energy",
+    "em_run", "free_energy", "DSC", "dsc_state_table", "dsc_state_count",
+    "dsc_log_joint", "dsc_selection_scores", "dsc_estep_point", "dsc_estep", "dsc_mstep",
 ]
 
 BSC, TSC, MCA, MMCA = "bsc", "tsc", "mca", "mmca"
@@ -370,3 +386,172 @@ def em_run(model: str, Y: np.ndarray, W0: np.ndarray, pi0: float, sigma0: float,
         if callback is not None:
             callback(it, W, pi, sigma, est)
     return F, W, pi, sigma
+
+
+# --------------------------------------------------------------------------
+# DSC: discrete latents phi_0 = 0, phi_1, ..., phi_{V-1}, categorical prior pv
+# --------------------------------------------------------------------------
+DSC = "dsc"
+
+
+def _check_dsc(phi, pv):
+    phi = np.asarray(phi, dtype=np.float64)
+    pv = np.asarray(pv, dtype=np.float64)
+    if phi.ndim != 1 or phi.shape != pv.shape or phi.shape[0] < 2 or phi[0] != 0.0:
+        raise ValueError("phi and pv hold V >= 2 entries and phi[0] = 0")
+    if np.any(phi[1:] == 0.0) or len(set(phi.tolist())) != len(phi):
+        raise ValueError("the non-zero values phi_1.. must be distinct and non-zero")
+    if np.any(pv <= 0.0) or abs(pv.sum() - 1.0) > 1e-12:
+        raise ValueError("pv must be positive and sum to 1")
+    return phi, pv
+
+
+def dsc_state_table(V: int, Hp: int, gamma: int) -> List[Tuple[Tuple[int, ...], Tuple[int, ...]]]:
+    """All states with support inside the H' slots and at most gamma actives,
+    as (slots, codes): ascending slot indices and the value code (1..V-1,
+    index into phi) of each active slot.  Order: k ascending; slot tuples
+    lexicographically; the codes of one support in mixed-radix counting
+    order, the digit of the first active slot least significant."""
+    out = []
+    for k in range(0, min(gamma, Hp) + 1):
+        for slots in combinations(range(Hp), k):
+            for count in range((V - 1) ** k):
+                codes, c = [], count
+                for _ in range(k):
+                    codes.append(1 + c % (V - 1))
+                    c //= V - 1
+                out.append((slots, tuple(codes)))
+    return out
+
+
+def dsc_state_count(V: int, Hp: int, gamma: int) -> int:
+    return sum(math.comb(Hp, k) * (V - 1) ** k for k in range(0, min(gamma, Hp) + 1))
+
+
+def _dsc_embed(tab, sel, H, phi):
+    """States of the table as H-vectors of values and of value codes."""
+    S = np.zeros((len(tab), H))
+    C = np.zeros((len(tab), H), dtype=np.int64)
+    for i, (slots, codes) in enumerate(tab):
+        for j, c in zip(slots, codes):
+            S[i, sel[j]] = phi[c]
+            C[i, sel[j]] = c
+    return S, C
+
+
+def dsc_log_joint(y, W, phi, pv, sigma, S, C) -> np.ndarray:
+    """log p(y, s | Theta) for every row (values S, codes C): the categorical
+    prior sum_h log pv[c_h] and the Gaussian noise with the direct residual."""
+    D = y.shape[0]
+    logp = np.log(pv)[C].sum(axis=1)
+    R = y[None, :] - S @ W.T
+    return logp - 0.5 * D * np.log(2.0 * np.pi * sigma * sigma) - (R * R).sum(axis=1) / (2.0 * sigma * sigma)
+
+
+def dsc_selection_scores(y, W, phi, pv, sigma) -> np.ndarray:
+    """r_h = max over v >= 1 of sigma^2 log(pv_v / pv_0) + 1/2||y||^2
+    - 1/2||y - phi_v W_h||^2: sigma^2 times the singleton log-joint of
+    (h, phi_v) up to h-independent terms."""
+    H = W.shape[1]
+    yy = 0.5 * float(y @ y)
+    best = np.full(H, -np.inf)
+    for v in range(1, len(phi)):
+        R = y[None, :] - phi[v] * W.T
+        r = sigma * sigma * np.log(pv[v] / pv[0]) + yy - 0.5 * (R * R).sum(axis=1)
+        best = np.maximum(best, r)
+    return best
+
+
+def dsc_estep_point(y, W, phi, pv, sigma, Hp, gamma, topk=0, tab=None, beta=1.0) -> Dict:
+    """Truncated posterior of one point for DSC (all float64); outputs as
+    estep_point plus v_mean[v] = expected number of latents taking phi_v."""
+    phi, pv = _check_dsc(phi, pv)
+    y = np.asarray(y, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    H = W.shape[1]
+    V = len(phi)
+    r = dsc_selection_scores(y, W, phi, pv, sigma)
+    sel, flagged = preselect(r, Hp)
+    if tab is None:
+        tab = dsc_state_table(V, Hp, gamma)
+    S, C = _dsc_embed(tab, sel, H, phi)
+    lj = dsc_log_joint(y, W, phi, pv, sigma, S, C)
+    logL = float(logsumexp(lj))
+    q = np.exp(beta * lj - logsumexp(beta * lj))
+    Ss, Cs = S[:, sel], C[:, sel]
+    v_mean = np.array([float(q @ (Cs == v).sum(axis=1)) for v in range(V)])
+    out = dict(sel=sel, flagged=flagged, scores=r, lj=lj, q=q, logL=logL,
+               s_mean=q @ Ss, ss_mean=(Ss * q[:, None]).T @ Ss,
+               k_mean=float(q @ (Cs != 0).sum(axis=1)), v_mean=v_mean)
+    if topk:
+        idx = np.arange(len(tab))
+        order = np.lexsort((idx, -q))[:topk]
+        out["top_index"] = order
+        out["top_q"] = q[order]
+    return out
+
+
+def dsc_estep(Y, W, phi, pv, sigma, Hp, gamma, topk=0, keep_posterior=False, beta=1.0) -> Dict:
+    """DSC E-step over all points with the M-step sums: A = sum y <s>^T,
+    B = sum <s s^T>, vcount[v] = sum_n <#latents at phi_v> (v = 0..V-1),
+    scal = [sum <k>, sum logL, sum ||y||^2, 0, N]."""
+    phi, pv = _check_dsc(phi, pv)
+    Y = np.asarray(Y, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    N, D = Y.shape
+    H = W.shape[1]
+    V = len(phi)
+    tab = dsc_state_table(V, Hp, gamma)
+    sel = np.zeros((N, Hp), dtype=np.int64)
+    flagged = np.zeros(N, dtype=bool)
+    logL = np.zeros(N)
+    s_mean = np.zeros((N, Hp))
+    k_mean = np.zeros(N)
+    top_index = np.zeros((N, topk), dtype=np.int64)
+    top_q = np.zeros((N, topk))
+    A = np.zeros((D, H))
+    B = np.zeros((H, H))
+    vcount = np.zeros(V)
+    post = []
+    for n in range(N):
+        p = dsc_estep_point(Y[n], W, phi, pv, sigma, Hp, gamma, topk, tab, beta)
+        sel[n], flagged[n], logL[n] = p["sel"], p["flagged"], p["logL"]
+        s_mean[n], k_mean[n] = p["s_mean"], p["k_mean"]
+        if topk:
+            top_index[n], top_q[n] = p["top_index"], p["top_q"]
+        c = p["sel"]
+        A[:, c] += np.outer(Y[n], p["s_mean"])
+        B[np.ix_(c, c)] += p["ss_mean"]
+        vcount += p["v_mean"]
+        if keep_posterior:
+            post.append((c, p["q"]))
+    vcount[0] = N * H - vcount[1:].sum()  # latents outside K's support are at phi_0
+    scal = np.array([k_mean.sum(), logL.sum(), float((Y * Y).sum()), 0.0, float(N)])
+    out = dict(sel=sel, flagged=flagged, logL=logL, s_mean=s_mean, k_mean=k_mean,
+               top_index=top_index, top_q=top_q, A=A, B=B, scal=scal, vcount=vcount,
+               table=tab, phi=phi)
+    if keep_posterior:
+        out["posterior"] = post
+    return out
+
+
+def dsc_mstep(Y, W_old, est):
+    """New (W, pv, sigma): W = A B^-1 on the latents with B_hh > 0 (others
+    keep their column); pv_v = vcount_v / (N H); sigma^2 = sum_n sum_s q
+    ||y - W_new s||^2 / (N D) as a direct sweep (needs keep_posterior)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    W_old = np.asarray(W_old, dtype=np.float64)
+    N, D = Y.shape
+    H = W_old.shape[1]
+    A, B = est["A"], est["B"]
+    W_new = W_old.copy()
+    act = np.diag(B) > 0
+    if act.any():
+        W_new[:, act] = np.linalg.solve(B[np.ix_(act, act)], A[:, act].T).T
+    pv_new = est["vcount"] / (N * H)
+    tot = 0.0
+    for n, (c, q) in enumerate(est["posterior"]):
+        S, _ = _dsc_embed(est["table"], c, H, est["phi"])
+        R = Y[n][None, :] - S @ W_new.T
+        tot += float(q @ (R * R).sum(axis=1))
+    return W_new, pv_new, float(np.sqrt(tot / (N * D)))
