@@ -14,13 +14,17 @@
  *   PROSPER_MCA  s in {0,1}^H,    Bernoulli(pi),           f_d = max_h s_h W_dh
  *   PROSPER_MMCA s in {0,1}^H,    Bernoulli(pi),           f_d = the s_h W_dh of largest
  *                magnitude (lower h on a tie); statistics and M-step as MCA
+ *   PROSPER_DSC  s_h in {phi_0 = 0, phi_1, ..., phi_{V-1}} (a given value set),
+ *                categorical prior p(s_h = phi_v) = pv_v,   f = W s
+ *                (discrete sparse coding; V = 2, phi = {0, 1} is BSC, and V = 3,
+ *                phi = {0, 1, -1} with pv_1 = pv_2 is TSC)
  *
  * Truncated posteriors (same section): for each data point y_n the library
  * preselects H' latents I_n (the "Hprime" argument of the API section) and
  * renormalises the exact posterior on
  *   K_n = { s : s_h = 0 for h not in I_n, and #nonzero(s) <= gamma }
  * ("gamma" of the API section).  |K_n| = sum_{k<=gamma} C(H',k) (V-1)^k with
- * V = 2 (BSC, MCA) or 3 (TSC).
+ * V = 2 (BSC, MCA, MMCA), 3 (TSC) or the DSC value count.
  *
  * Conventions (all entry points)
  *  - Every device pointer is owned by the caller; the library never frees one.
@@ -54,7 +58,9 @@ typedef enum {
     PROSPER_ETIMEDOUT = -6  /* serving wait ran out of time; request still live */
 } prosper_status;
 
-typedef enum { PROSPER_BSC = 0, PROSPER_TSC = 1, PROSPER_MCA = 2, PROSPER_MMCA = 3 } prosper_model;
+typedef enum {
+    PROSPER_BSC = 0, PROSPER_TSC = 1, PROSPER_MCA = 2, PROSPER_MMCA = 3, PROSPER_DSC = 4
+} prosper_model;
 
 /* Precision of the N x D x H projection contraction (W^T y for all latents).
  *  PROSPER_FP32: FP32 MFMA (v_mfma_f32_16x16x4_f32), FP32 accumulation.
@@ -85,6 +91,8 @@ typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1 } prosper_precision;
 #define PROSPER_MAX_H        1024
 #define PROSPER_MAX_TOPK     8
 #define PROSPER_MAX_STATES   (1 << 20)
+#define PROSPER_MAX_VALUES   8   /* DSC: V <= 8 */
+#define PROSPER_DSC_MAX_GAMMA 10 /* DSC: gamma <= 10 (3-bit value codes of the actives) */
 
 typedef struct {
     int32_t model;          /* prosper_model */
@@ -108,6 +116,13 @@ typedef struct {
                                (0, 1]; 0 stands for 1 (no annealing).  Moments, top-k
                                and statistics use the tempered q; logL stays
                                untempered.  beta != 1 runs the table-driven state walk. */
+    /* DSC only (ignored by the other models): */
+    int32_t nvalues;        /* V, 2..PROSPER_MAX_VALUES */
+    float   phi[PROSPER_MAX_VALUES];  /* phi[0] = 0; phi[1..V-1] finite, non-zero, distinct */
+    double  pv[PROSPER_MAX_VALUES];   /* prior pv[0..V-1], each > 0, summing to 1 (within
+                               1e-9).  With theta_dev set they are read from the device
+                               instead: theta_dev = {pi, sigma, pv_0, ..., pv_{V-1}}
+                               (pi unused), the layout prosper_mstep writes for DSC. */
 } prosper_args;
 
 /* Per-point outputs of the E-step; any pointer may be NULL to skip it.
@@ -119,7 +134,10 @@ typedef struct {
                                     (natural log, all constants included) */
     uint32_t* top_mask; /* N x topk slot masks of the most probable states
                            (bit j = slot j, i.e. latent sel[n][j], is non-zero);
-                           TSC: N x topk x 2 = {active mask, minus-sign mask} */
+                           TSC: N x topk x 2 = {active mask, minus-sign mask};
+                           DSC: N x topk x 4 = {active mask, then three bit planes of
+                           the value codes: bit j of plane p is bit p of the code
+                           v (s = phi_v) of slot j} */
     float*    top_q;    /* N x topk their posterior probabilities q_n(s),
                            descending; equal q ordered by canonical state order */
     uint8_t*  flagged;  /* N        1 if the H'-th and (H'+1)-th selection scores
@@ -129,18 +147,21 @@ typedef struct {
 /* Sufficient statistics for the M-step, accumulated (added) by prosper_estep
  * when args.accumulate = 1.  The caller zeroes them before the first E-step
  * of an iteration.  Device pointers.
- *   BSC/TSC:  A (D x H) += y_n <s>_n^T ;  B (H x H, upper triangle incl.
+ *   BSC/TSC/DSC: A (D x H) += y_n <s>_n^T ;  B (H x H, upper triangle incl.
  *             diagonal in row-major h <= h') += <s s^T>_n
  *   MCA:      A (D x H) += R_n o y_n  (numerator);  B (D x H) += R_n
  *             (denominator), R_n[d,h] = posterior mass of the states whose max
  *             over active components at pixel d is attained first by h and is > 0
  *   scal (5 doubles): [0] sum_n <#nonzero(s)>  [1] sum_n logL_n
  *             [2] sum_n ||y_n||^2  [3] sum_n <||y_n - f(s)||^2> (MCA only)
- *             [4] N */
+ *             [4] N
+ *   vcount (DSC only, V doubles): [v] += sum_n <number of latents at phi_v>
+ *             for v = 1..V-1 ([0] is not touched) */
 typedef struct {
     float*  A;
     float*  B;
     double* scal;
+    double* vcount;
 } prosper_acc;
 
 typedef struct prosper_ctx prosper_ctx;
@@ -181,6 +202,16 @@ prosper_status prosper_state_count(int32_t model, int32_t Hprime, int32_t gamma,
  * (zero for BSC/MCA; sgn may be NULL). */
 prosper_status prosper_state_table(int32_t model, int32_t Hprime, int32_t gamma,
                                    uint32_t* act, uint32_t* sgn, int64_t capacity);
+
+/* DSC counterparts of the two calls above: |K| for V values, and the table
+ * in the same order with codes[k] = the value codes (1..V-1) of the active
+ * slots, 3 bits each, the lowest active slot in bits 0-2; the codes of one
+ * support run in mixed-radix counting order (base V-1), the digit of the
+ * lowest active slot least significant.  gamma <= PROSPER_DSC_MAX_GAMMA. */
+prosper_status prosper_dsc_state_count(int32_t nvalues, int32_t Hprime, int32_t gamma,
+                                       int64_t* count);
+prosper_status prosper_dsc_state_table(int32_t nvalues, int32_t Hprime, int32_t gamma,
+                                       uint32_t* act, uint32_t* codes, int64_t capacity);
 
 /* E-step ---------------------------------------------------------------- */
 
@@ -232,8 +263,12 @@ prosper_status prosper_estep_static(const prosper_args* args, const float* Y, co
  *            sigma^2 = (scal[2] - 2 tr(W_new^T A) + tr(W_new^T W_new B))/(N D)
  *   MCA:     W_new[d,h] = A[d,h]/B[d,h] where B[d,h] > 0 (else W_old),
  *            pi as above, sigma^2 = scal[3]/(N D)
- * W_old and W_new (D x H FP32) may alias.  theta_new (device, 2 doubles) gets
- * {pi, sigma}; it may equal args->theta_dev.  args supplies model, D, H.
+ *   DSC:     W and sigma as BSC; pv_v = vcount[v]/(N H) for v >= 1,
+ *            pv_0 = 1 - sum_{v>=1} pv_v (the expected share of latents at each
+ *            value); needs acc->vcount and args->nvalues
+ * W_old and W_new (D x H FP32) may alias.  theta_new (device) gets {pi, sigma}
+ * (2 doubles), for DSC {pi, sigma, pv_0, ..., pv_{V-1}} (2 + V doubles); it
+ * may equal args->theta_dev.  args supplies model, D, H (and nvalues).
  * Errors: EINVAL for a NULL pointer, an unknown model or D, H out of range;
  * EDEVICE for a HIP failure (message in prosper_last_error). */
 prosper_status prosper_mstep(prosper_ctx* ctx, const prosper_args* args,
@@ -257,7 +292,8 @@ typedef struct prosper_server prosper_server;
  * concurrently on `n_streams` HIP streams (1..8).  queue_capacity bounds
  * pending requests.  The server holds mem_budget_bytes of device memory and
  * twice that of pinned host memory (output staging, and an ingress area into
- * which submit copies request inputs). */
+ * which submit copies request inputs).  Models: BSC, TSC, MCA, MMCA (EINVAL
+ * for DSC, whose prior has no place in this call). */
 prosper_status prosper_serve(prosper_ctx* ctx, const float* W, int32_t W_on_device,
                              int32_t model, int32_t D, int32_t H, double pi,
                              double sigma, int32_t precision, size_t mem_budget_bytes,

@@ -462,16 +462,22 @@ def dsc_selection_scores(y, W, phi, pv, sigma) -> np.ndarray:
     return best
 
 
-def dsc_estep_point(y, W, phi, pv, sigma, Hp, gamma, topk=0, tab=None, beta=1.0) -> Dict:
+def dsc_estep_point(y, W, phi, pv, sigma, Hp, gamma, topk=0, tab=None, beta=1.0,
+                    sel=None) -> Dict:
     """Truncated posterior of one point for DSC (all float64); outputs as
-    estep_point plus v_mean[v] = expected number of latents taking phi_v."""
+    estep_point plus v_mean[v] = expected number of latents taking phi_v.
+    `sel` (optional) replaces the preselected set, as in estep_point."""
     phi, pv = _check_dsc(phi, pv)
     y = np.asarray(y, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     H = W.shape[1]
     V = len(phi)
     r = dsc_selection_scores(y, W, phi, pv, sigma)
-    sel, flagged = preselect(r, Hp)
+    if sel is None:
+        sel, flagged = preselect(r, Hp)
+    else:
+        flagged = preselect(r, Hp)[1]
+        sel = np.sort(np.asarray(sel, dtype=np.int64))
     if tab is None:
         tab = dsc_state_table(V, Hp, gamma)
     S, C = _dsc_embed(tab, sel, H, phi)
@@ -491,10 +497,13 @@ def dsc_estep_point(y, W, phi, pv, sigma, Hp, gamma, topk=0, tab=None, beta=1.0)
     return out
 
 
-def dsc_estep(Y, W, phi, pv, sigma, Hp, gamma, topk=0, keep_posterior=False, beta=1.0) -> Dict:
+def dsc_estep(Y, W, phi, pv, sigma, Hp, gamma, topk=0, keep_posterior=False, beta=1.0,
+              sel=None) -> Dict:
     """DSC E-step over all points with the M-step sums: A = sum y <s>^T,
     B = sum <s s^T>, vcount[v] = sum_n <#latents at phi_v> (v = 0..V-1),
-    scal = [sum <k>, sum logL, sum ||y||^2, 0, N]."""
+    scal = [sum <k>, sum logL, sum ||y||^2, 0, N].  `sel` (optional, N x H')
+    replaces the preselection point by point."""
+    forced = sel
     phi, pv = _check_dsc(phi, pv)
     Y = np.asarray(Y, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
@@ -514,7 +523,8 @@ def dsc_estep(Y, W, phi, pv, sigma, Hp, gamma, topk=0, keep_posterior=False, bet
     vcount = np.zeros(V)
     post = []
     for n in range(N):
-        p = dsc_estep_point(Y[n], W, phi, pv, sigma, Hp, gamma, topk, tab, beta)
+        p = dsc_estep_point(Y[n], W, phi, pv, sigma, Hp, gamma, topk, tab, beta,
+                            None if forced is None else forced[n])
         sel[n], flagged[n], logL[n] = p["sel"], p["flagged"], p["logL"]
         s_mean[n], k_mean[n] = p["s_mean"], p["k_mean"]
         if topk:

@@ -14,12 +14,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # always the in-tree build: tests and the benchmark must exercise this library
 LIB_PATH = os.path.join(_HERE, "libprosper.so")
 
-MODELS = {"bsc": 0, "tsc": 1, "mca": 2, "mmca": 3}
+MODELS = {"bsc": 0, "tsc": 1, "mca": 2, "mmca": 3, "dsc": 4}
 PRECISIONS = {"fp32": 0, "bf16": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY",
           -5: "ENOTFOUND", -6: "ETIMEDOUT"}
 
 MAX_HPRIME, MAX_D, MAX_H, MAX_TOPK, MAX_STATES = 32, 1024, 1024, 8, 1 << 20
+MAX_VALUES = 8  # DSC value count
 
 
 class ProsperError(RuntimeError):
@@ -36,7 +37,9 @@ class Args(C.Structure):
                 ("D", C.c_int32), ("H", C.c_int32), ("Hprime", C.c_int32),
                 ("gamma", C.c_int32), ("pi", C.c_double), ("sigma", C.c_double),
                 ("theta_dev", C.c_void_p), ("topk", C.c_int32), ("accumulate", C.c_int32),
-                ("flags", C.c_uint32), ("beta", C.c_float)]
+                ("flags", C.c_uint32), ("beta", C.c_float),
+                ("nvalues", C.c_int32), ("phi", C.c_float * MAX_VALUES),
+                ("pv", C.c_double * MAX_VALUES)]
 
 
 class PointOut(C.Structure):
@@ -45,7 +48,8 @@ class PointOut(C.Structure):
 
 
 class Acc(C.Structure):
-    _fields_ = [("A", C.c_void_p), ("B", C.c_void_p), ("scal", C.c_void_p)]
+    _fields_ = [("A", C.c_void_p), ("B", C.c_void_p), ("scal", C.c_void_p),
+                ("vcount", C.c_void_p)]
 
 
 EXPORTS = [
@@ -54,7 +58,7 @@ EXPORTS = [
     "prosper_estep", "prosper_mstep", "prosper_serve", "prosper_serve_submit",
     "prosper_serve_wait", "prosper_serve_wait_stages", "prosper_serve_stop",
     "prosper_profile", "prosper_profile_read",
-    "prosper_estep_static",
+    "prosper_estep_static", "prosper_dsc_state_count", "prosper_dsc_state_table",
 ]
 
 _lib: Optional[C.CDLL] = None
@@ -82,6 +86,10 @@ def load() -> C.CDLL:
     lib.prosper_state_count.restype = i32
     lib.prosper_state_table.argtypes = [i32, i32, i32, vp, vp, i64]
     lib.prosper_state_table.restype = i32
+    lib.prosper_dsc_state_count.argtypes = [i32, i32, i32, C.POINTER(i64)]
+    lib.prosper_dsc_state_count.restype = i32
+    lib.prosper_dsc_state_table.argtypes = [i32, i32, i32, vp, vp, i64]
+    lib.prosper_dsc_state_table.restype = i32
     lib.prosper_estep.argtypes = [vp, C.POINTER(Args), vp, vp, C.POINTER(PointOut),
                                   C.POINTER(Acc), vp]
     lib.prosper_estep.restype = i32
@@ -122,9 +130,25 @@ def check(status: int, ctx=None):
 
 def make_args(model: str, precision: str, N: int, D: int, H: int, Hprime: int, gamma: int,
               pi: float = 0.5, sigma: float = 1.0, theta_dev: Optional[int] = None,
-              topk: int = 0, accumulate: int = 0, flags: int = 0, beta: float = 1.0) -> Args:
-    return Args(MODELS[model], PRECISIONS[precision], N, D, H, Hprime, gamma, float(pi),
-                float(sigma), theta_dev, topk, accumulate, flags, float(beta))
+              topk: int = 0, accumulate: int = 0, flags: int = 0, beta: float = 1.0,
+              phi=None, pv=None) -> Args:
+    """Argument block; `phi` and `pv` (DSC) are the value set and its prior."""
+    a = Args(MODELS[model], PRECISIONS[precision], N, D, H, Hprime, gamma, float(pi),
+             float(sigma), theta_dev, topk, accumulate, flags, float(beta))
+    if phi is not None:
+        phi = [float(x) for x in phi]
+        if len(phi) > MAX_VALUES:
+            raise ValueError(f"at most {MAX_VALUES} DSC values")
+        a.nvalues = len(phi)
+        for v, x in enumerate(phi):
+            a.phi[v] = x
+    if pv is not None:
+        pv = [float(x) for x in pv]
+        if len(pv) > MAX_VALUES:
+            raise ValueError(f"at most {MAX_VALUES} DSC values")
+        for v, x in enumerate(pv):
+            a.pv[v] = x
+    return a
 
 
 def state_count(model: str, Hprime: int, gamma: int) -> int:
@@ -143,6 +167,24 @@ def state_table(model: str, Hprime: int, gamma: int):
                                      act.ctypes.data_as(C.c_void_p),
                                      sgn.ctypes.data_as(C.c_void_p), n))
     return act, sgn
+
+
+def dsc_state_count(nvalues: int, Hprime: int, gamma: int) -> int:
+    n = C.c_int64(0)
+    check(load().prosper_dsc_state_count(nvalues, Hprime, gamma, C.byref(n)))
+    return n.value
+
+
+def dsc_state_table(nvalues: int, Hprime: int, gamma: int):
+    """DSC state table from the library: active masks and packed value codes."""
+    import numpy as np
+    n = dsc_state_count(nvalues, Hprime, gamma)
+    act = np.zeros(n, dtype=np.uint32)
+    codes = np.zeros(n, dtype=np.uint32)
+    check(load().prosper_dsc_state_table(nvalues, Hprime, gamma,
+                                         act.ctypes.data_as(C.c_void_p),
+                                         codes.ctypes.data_as(C.c_void_p), n))
+    return act, codes
 
 
 def validate(args: Args) -> int:

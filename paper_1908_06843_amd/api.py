@@ -4,6 +4,8 @@
     out = estep(Y, W, pi, sigma, Hprime=12, gamma=4)           # BSC, FP32
     acc = new_acc("bsc", D, H); estep(..., acc=acc)             # accumulate statistics
     W1, theta = mstep(acc, W, model="bsc")                      # FP64 M-step on device
+    estep(Y, W, sigma=s, Hprime=8, gamma=3, model="dsc",        # discrete values phi_v
+          phi=(0, 1, -1, 2), pv=(0.7, 0.1, 0.1, 0.1))
 
 All tensors live on the GPU; every step of the computation runs in
 libprosper.so.  Outputs are valid once the current stream is synchronised.
@@ -18,11 +20,13 @@ import torch
 from . import _lib
 
 __all__ = ["Context", "context", "estep", "mstep", "new_acc", "zero_acc", "state_count",
-           "state_table", "ProsperError"]
+           "state_table", "dsc_state_count", "dsc_state_table", "ProsperError"]
 
 ProsperError = _lib.ProsperError
 state_count = _lib.state_count
 state_table = _lib.state_table
+dsc_state_count = _lib.dsc_state_count
+dsc_state_table = _lib.dsc_state_table
 
 
 class Context:
@@ -76,13 +80,23 @@ def _dev_f32(name: str, t: torch.Tensor) -> torch.Tensor:
     return t
 
 
-def new_acc(model: str, D: int, H: int, device=None) -> Dict[str, torch.Tensor]:
-    """Zeroed M-step accumulators (A: D x H, B: H x H, or D x H for MCA/MMCA, scal: 5 doubles)."""
+def new_acc(model: str, D: int, H: int, device=None, nvalues: int = 0) -> Dict[str, torch.Tensor]:
+    """Zeroed M-step accumulators (A: D x H, B: H x H, or D x H for MCA/MMCA, scal: 5 doubles;
+    DSC also vcount: `nvalues` doubles)."""
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
     Bshape = (D, H) if model in ("mca", "mmca") else (H, H)
-    return {"A": torch.zeros((D, H), dtype=torch.float32, device=dev),
-            "B": torch.zeros(Bshape, dtype=torch.float32, device=dev),
-            "scal": torch.zeros(5, dtype=torch.float64, device=dev)}
+    acc = {"A": torch.zeros((D, H), dtype=torch.float32, device=dev),
+           "B": torch.zeros(Bshape, dtype=torch.float32, device=dev),
+           "scal": torch.zeros(5, dtype=torch.float64, device=dev)}
+    if model == "dsc":
+        if nvalues < 2:
+            raise ValueError("DSC accumulators need nvalues >= 2")
+        acc["vcount"] = torch.zeros(nvalues, dtype=torch.float64, device=dev)
+    return acc
+
+
+def _acc_struct(acc: Dict[str, torch.Tensor]):
+    return _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]), _ptr(acc.get("vcount")))
 
 
 def zero_acc(acc: Dict[str, torch.Tensor]):
@@ -98,7 +112,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
           out: Optional[Dict[str, torch.Tensor]] = None,
           ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None,
           factor_b: bool = False, static: bool = False,
-          beta: float = 1.0) -> Dict[str, torch.Tensor]:
+          beta: float = 1.0, phi: Optional[Sequence[float]] = None,
+          pv: Optional[Sequence[float]] = None) -> Dict[str, torch.Tensor]:
     """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
 
     Returns the requested per-point outputs: sel (N x H' int32), s_mean
@@ -112,6 +127,9 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     intermediates live in the library's fixed device array); no context.
     `beta` is the posterior temperature of deterministic annealing (q
     proportional to p(y, s)^beta; logL untempered).
+    DSC (model="dsc"): `phi` is the value set (phi[0] = 0) and `pv` its prior
+    (ignored when `theta` = (pi, sigma, pv_0 .. pv_{V-1}) is given); top_mask
+    is N x topk x 4 (active mask, three bit planes of the value codes).
     """
     _dev_f32("Y", Y)
     _dev_f32("W", W)
@@ -142,17 +160,20 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     if "flagged" in want or "flagged" in out:
         res["flagged"] = get("flagged", (N,), torch.uint8)
     if topk:
-        mshape = (N, topk, 2) if model == "tsc" else (N, topk)
+        mshape = {"tsc": (N, topk, 2), "dsc": (N, topk, 4)}.get(model, (N, topk))
         res["top_mask"] = get("top_mask", mshape, torch.int32)
         res["top_q"] = get("top_q", (N, topk), torch.float32)
     po = _lib.PointOut(_ptr(res.get("sel")), _ptr(res.get("s_mean")), _ptr(res.get("logL")),
                        _ptr(res.get("top_mask")), _ptr(res.get("top_q")), _ptr(res.get("flagged")))
     accs = None
     if acc is not None:
-        accs = _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]))
+        accs = _acc_struct(acc)
+    if model == "dsc" and phi is None:
+        raise ValueError("DSC needs the value set phi")
     args = _lib.make_args(model, precision, N, D, H, Hprime, gamma, pi, sigma,
                           _ptr(theta), topk, 1 if acc is not None else 0,
-                          _lib.FLAG_FACTOR_B if factor_b else 0, beta)
+                          _lib.FLAG_FACTOR_B if factor_b else 0, beta,
+                          phi if model == "dsc" else None, pv if model == "dsc" else None)
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lib = _lib.load()
     if static:
@@ -171,16 +192,19 @@ def mstep(acc: Dict[str, torch.Tensor], W_old: torch.Tensor, *, model: str = "bs
           W_new: Optional[torch.Tensor] = None, theta_new: Optional[torch.Tensor] = None,
           ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None):
     """FP64 M-step on the device.  Returns (W_new, theta_new) where theta_new
-    holds (pi, sigma) as two doubles on the device."""
+    holds (pi, sigma) as two doubles on the device; DSC: (pi, sigma, pv_0 ..
+    pv_{V-1}), V the length of acc["vcount"]."""
     _dev_f32("W_old", W_old)
     D, H = W_old.shape
     ctx = ctx or context(W_old.device.index)
+    nv = int(acc["vcount"].numel()) if model == "dsc" else 0
     if W_new is None:
         W_new = torch.empty_like(W_old)
     if theta_new is None:
-        theta_new = torch.empty(2, dtype=torch.float64, device=W_old.device)
+        theta_new = torch.empty(2 + nv, dtype=torch.float64, device=W_old.device)
     args = _lib.make_args(model, "fp32", 0, D, H, 1, 0)
-    accs = _lib.Acc(_ptr(acc["A"]), _ptr(acc["B"]), _ptr(acc["scal"]))
+    args.nvalues = nv
+    accs = _acc_struct(acc)
     st = (stream or torch.cuda.current_stream(W_old.device)).cuda_stream
     _lib.check(_lib.load().prosper_mstep(ctx.handle, C.byref(args), C.byref(accs), _ptr(W_old),
                                          _ptr(W_new), _ptr(theta_new), C.c_void_p(st)),

@@ -123,9 +123,11 @@ hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes) {
 }
 
 // Canonical enumeration: k ascending, slot tuples lexicographic, TSC sign
-// codes counting up (bit i of the code = sign of the i-th active slot).
+// codes counting up (bit i of the code = sign of the i-th active slot), DSC
+// value codes of one support counting up in base V-1 (digit i, plus one, is
+// the value code of the i-th active slot, stored in bits 3i .. 3i+2).
 void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
-                 std::vector<uint32_t>& sgn) {
+                 std::vector<uint32_t>& sgn, int nv) {
   act.clear();
   sgn.clear();
   const int kmax = gamma < Hp ? gamma : Hp;
@@ -135,7 +137,20 @@ void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
     while (true) {
       uint32_t a = 0;
       for (int i = 0; i < k; ++i) a |= 1u << c[i];
-      if (model == PROSPER_TSC) {
+      if (model == PROSPER_DSC) {
+        int64_t ncodes = 1;
+        for (int i = 0; i < k; ++i) ncodes *= nv - 1;
+        for (int64_t code = 0; code < ncodes; ++code) {
+          uint32_t w = 0;
+          int64_t r = code;
+          for (int i = 0; i < k; ++i) {
+            w |= (uint32_t)(1 + r % (nv - 1)) << (3 * i);
+            r /= nv - 1;
+          }
+          act.push_back(a);
+          sgn.push_back(w);
+        }
+      } else if (model == PROSPER_TSC) {
         for (uint32_t code = 0; code < (1u << k); ++code) {
           uint32_t s = 0;
           for (int i = 0; i < k; ++i)
@@ -158,9 +173,14 @@ void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
 }
 
 prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* out,
-                            std::string* msg) {
-  if (model != PROSPER_BSC && model != PROSPER_TSC && !is_max_model(model)) {
+                            std::string* msg, int nv) {
+  if (model != PROSPER_BSC && model != PROSPER_TSC && model != PROSPER_DSC &&
+      !is_max_model(model)) {
     if (msg) *msg = "unknown model";
+    return PROSPER_EINVAL;
+  }
+  if (model == PROSPER_DSC && (nv < 2 || nv > PROSPER_MAX_VALUES)) {
+    if (msg) *msg = "DSC nvalues outside 2..8";
     return PROSPER_EINVAL;
   }
   if (Hp < 1 || Hp > PROSPER_MAX_HPRIME) {
@@ -171,9 +191,13 @@ prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* o
     if (msg) *msg = "gamma outside 0..Hprime";
     return PROSPER_EINVAL;
   }
-  const int V1 = (model == PROSPER_TSC) ? 2 : 1;
+  if (model == PROSPER_DSC && gamma > PROSPER_DSC_MAX_GAMMA) {
+    if (msg) *msg = "DSC gamma above 10 (3-bit value codes of the actives)";
+    return PROSPER_EINVAL;
+  }
+  const int V1 = (model == PROSPER_TSC) ? 2 : (model == PROSPER_DSC ? nv - 1 : 1);
   double total = 0.0;
-  int64_t cnt = 0;
+  int64_t cnt = 0, pw = 1;
   for (int k = 0; k <= gamma; ++k) {
     const double t = (double)binom(Hp, k) * std::pow((double)V1, k);
     total += t;
@@ -181,7 +205,8 @@ prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* o
       if (msg) *msg = "truncated state set larger than PROSPER_MAX_STATES";
       return PROSPER_EINVAL;
     }
-    cnt += binom(Hp, k) * ((int64_t)1 << (V1 == 2 ? k : 0));
+    cnt += binom(Hp, k) * pw;
+    pw *= V1;
   }
   *out = cnt;
   return PROSPER_OK;
@@ -195,9 +220,46 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "args is NULL";
     return PROSPER_EINVAL;
   }
-  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && !is_max_model(a->model)) {
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_DSC &&
+      !is_max_model(a->model)) {
     *msg = "unknown model";
     return PROSPER_EINVAL;
+  }
+  const bool dsc = a->model == PROSPER_DSC;
+  if (dsc) {
+    if (a->nvalues < 2 || a->nvalues > PROSPER_MAX_VALUES) {
+      *msg = "DSC nvalues outside 2..8";
+      return PROSPER_EINVAL;
+    }
+    if (a->phi[0] != 0.0f) {
+      *msg = "DSC phi[0] must be 0";
+      return PROSPER_EINVAL;
+    }
+    for (int v = 1; v < a->nvalues; ++v) {
+      if (!std::isfinite(a->phi[v]) || a->phi[v] == 0.0f) {
+        *msg = "DSC phi[1..V-1] must be finite and non-zero";
+        return PROSPER_EINVAL;
+      }
+      for (int w = 1; w < v; ++w)
+        if (a->phi[w] == a->phi[v]) {
+          *msg = "DSC phi values must be distinct";
+          return PROSPER_EINVAL;
+        }
+    }
+    if (!a->theta_dev) {
+      double sum = 0.0;
+      for (int v = 0; v < a->nvalues; ++v) {
+        if (!(a->pv[v] > 0.0) || !std::isfinite(a->pv[v])) {
+          *msg = "DSC pv entries must be positive";
+          return PROSPER_EINVAL;
+        }
+        sum += a->pv[v];
+      }
+      if (std::fabs(sum - 1.0) > 1e-9) {
+        *msg = "DSC pv must sum to 1";
+        return PROSPER_EINVAL;
+      }
+    }
   }
   if (a->precision != PROSPER_FP32 && a->precision != PROSPER_BF16) {
     *msg = "unknown precision";
@@ -224,7 +286,7 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     return PROSPER_EINVAL;
   }
   if (!a->theta_dev) {
-    if (!(a->pi > 0.0 && a->pi < 1.0)) {
+    if (!dsc && !(a->pi > 0.0 && a->pi < 1.0)) {
       *msg = "pi outside (0, 1)";
       return PROSPER_EINVAL;
     }
@@ -250,11 +312,11 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     return PROSPER_EINVAL;
   }
   if ((a->flags & PROSPER_FLAG_FACTOR_B) && (!a->accumulate || is_max_model(a->model))) {
-    *msg = "PROSPER_FLAG_FACTOR_B needs accumulate = 1 and a linear model (BSC/TSC)";
+    *msg = "PROSPER_FLAG_FACTOR_B needs accumulate = 1 and a linear model (BSC/TSC/DSC)";
     return PROSPER_EINVAL;
   }
   int64_t ns = 0;
-  prosper_status st = count_states(a->model, a->Hprime, a->gamma, &ns, msg);
+  prosper_status st = count_states(a->model, a->Hprime, a->gamma, &ns, msg, a->nvalues);
   if (st != PROSPER_OK) return st;
   if (a->topk > ns) {
     *msg = "topk larger than the truncated state set";
@@ -271,15 +333,18 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
   return PROSPER_OK;
 }
 
-prosper_status get_table(prosper_ctx* c, int model, int Hp, int gamma, Table** out) {
-  auto key = std::make_tuple(is_max_model(model) ? PROSPER_BSC : model, Hp, gamma);
+prosper_status get_table(prosper_ctx* c, int model, int Hp, int gamma, Table** out,
+                         int nv = 0) {
+  // DSC tables differ by the value count
+  const int kind = is_max_model(model) ? PROSPER_BSC : (model == PROSPER_DSC ? 100 + nv : model);
+  auto key = std::make_tuple(kind, Hp, gamma);
   auto it = c->tables.find(key);
   if (it != c->tables.end()) {
     *out = &it->second;
     return PROSPER_OK;
   }
   std::vector<uint32_t> act, sgn;
-  build_table(model, Hp, gamma, act, sgn);
+  build_table(model, Hp, gamma, act, sgn, nv);
   Table t;
   t.count = (int64_t)act.size();
   hipError_t e = hipMalloc(&t.act, act.size() * 4);
@@ -416,6 +481,10 @@ prosper_status check_estep(const prosper_args* a, const float* Y, const float* W
     *msg = "accumulate=1 needs acc->A, acc->B and acc->scal";
     return PROSPER_EINVAL;
   }
+  if (a->accumulate && a->model == PROSPER_DSC && !acc->vcount) {
+    *msg = "DSC with accumulate=1 needs acc->vcount";
+    return PROSPER_EINVAL;
+  }
   if (a->topk > 0 && out && !out->top_mask && !out->top_q) {
     *msg = "topk > 0 needs top_mask or top_q";
     return PROSPER_EINVAL;
@@ -509,7 +578,8 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
   int tree_blocks = 0;
   hipError_t e = timed(c, "prep", s, [&] {
     hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
-                                      sc.redo_count, s, sc.defer_count, args_beta(a));
+                                      sc.redo_count, s, sc.defer_count, args_beta(a),
+                                      dsc_params(a));
     return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp, p, s) : e2;
   });
   if (e == hipSuccess)
@@ -517,7 +587,12 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
       return launch_project_select(model, prec, Y, N, D, Dp, H, Hp, p, sc, flagged, scal, s);
     });
   if (e == hipSuccess)
-    e = timed(c, is_max_model(model) ? "states_max" : "states_lin", s, [&] {
+    e = timed(c, is_max_model(model) ? "states_max"
+                 : (model == PROSPER_DSC ? "states_dsc" : "states_lin"), s, [&] {
+      if (model == PROSPER_DSC)
+        return launch_states_dsc(Hp, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask, top_q,
+                                 a->topk, Aacc != nullptr, Aacc ? acc->vcount : nullptr, scal,
+                                 s);
       if (is_max_model(model))
         return launch_states_max(model, Hp, a->gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL,
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
@@ -560,8 +635,9 @@ int32_t prosper_profile_read(prosper_ctx* c, int32_t cap, const char** names, do
   for (const std::string& n : c->prof_order) {
     if (i < cap) {
       // the names are string literals of this library
-      static const char* known[] = {"prep",  "project_select", "states_lin", "states_max",
-                                    "stats", "mstep_factor",   "mstep"};
+      static const char* known[] = {"prep",         "project_select", "states_lin",
+                                    "states_max",   "states_dsc",     "stats",
+                                    "mstep_factor", "mstep"};
       const char* nm = "";
       for (const char* k : known)
         if (n == k) nm = k;
@@ -601,6 +677,30 @@ prosper_status prosper_state_table(int32_t model, int32_t Hprime, int32_t gamma,
   build_table(model, Hprime, gamma, a, s);
   std::memcpy(act, a.data(), a.size() * 4);
   if (sgn) std::memcpy(sgn, s.data(), s.size() * 4);
+  return PROSPER_OK;
+}
+
+prosper_status prosper_dsc_state_count(int32_t nvalues, int32_t Hprime, int32_t gamma,
+                                       int64_t* count) {
+  std::string msg;
+  if (!count) return fail(nullptr, PROSPER_EINVAL, "count is NULL");
+  prosper_status st = count_states(PROSPER_DSC, Hprime, gamma, count, &msg, nvalues);
+  if (st != PROSPER_OK) g_tls_err = msg;
+  return st;
+}
+
+prosper_status prosper_dsc_state_table(int32_t nvalues, int32_t Hprime, int32_t gamma,
+                                       uint32_t* act, uint32_t* codes, int64_t capacity) {
+  int64_t n = 0;
+  std::string msg;
+  prosper_status st = count_states(PROSPER_DSC, Hprime, gamma, &n, &msg, nvalues);
+  if (st != PROSPER_OK) return fail(nullptr, st, msg);
+  if (!act || !codes) return fail(nullptr, PROSPER_EINVAL, "act or codes is NULL");
+  if (capacity < n) return fail(nullptr, PROSPER_EINVAL, "capacity smaller than the state count");
+  std::vector<uint32_t> a, s;
+  build_table(PROSPER_DSC, Hprime, gamma, a, s, nvalues);
+  std::memcpy(act, a.data(), a.size() * 4);
+  std::memcpy(codes, s.data(), s.size() * 4);
   return PROSPER_OK;
 }
 
@@ -667,7 +767,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   const int Dp = padded_depth(D);
 
   Table* tab = nullptr;
-  st = get_table(c, model, Hp, a->gamma, &tab);
+  st = get_table(c, model, Hp, a->gamma, &tab, model == PROSPER_DSC ? a->nvalues : 0);
   if (st != PROSPER_OK) return st;
 
   e = ensure(c->prep, prep_bytes(Dp, H, prec));
@@ -720,12 +820,17 @@ prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prospe
                              const float* W_old, float* W_new, double* theta_new, void* stream) {
   if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
   if (!a) return fail(c, PROSPER_EINVAL, "args is NULL");
-  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && !is_max_model(a->model))
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_DSC &&
+      !is_max_model(a->model))
     return fail(c, PROSPER_EINVAL, "unknown model");
   if (a->D < 1 || a->D > PROSPER_MAX_D || a->H < 1 || a->H > PROSPER_MAX_H)
     return fail(c, PROSPER_EINVAL, "D or H out of range");
   if (!acc || !acc->A || !acc->B || !acc->scal || !W_old || !W_new || !theta_new)
     return fail(c, PROSPER_EINVAL, "NULL pointer argument");
+  const bool dsc = a->model == PROSPER_DSC;
+  if (dsc && (a->nvalues < 2 || a->nvalues > PROSPER_MAX_VALUES))
+    return fail(c, PROSPER_EINVAL, "DSC nvalues outside 2..8");
+  if (dsc && !acc->vcount) return fail(c, PROSPER_EINVAL, "DSC M-step needs acc->vcount");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -741,6 +846,8 @@ prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prospe
     return launch_mstep(a->model, a->D, a->H, acc->A, acc->B, acc->scal, W_old, W_new, theta_new,
                         c->mwork.p, s);
   });
+  if (e == hipSuccess && dsc)
+    e = launch_mstep_dsc_prior(a->H, a->nvalues, acc->scal, acc->vcount, theta_new, s);
   if (e != hipSuccess) return hip_fail(c, e, "M-step launch");
   return PROSPER_OK;
 }

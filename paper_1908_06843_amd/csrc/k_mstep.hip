@@ -438,6 +438,29 @@ __global__ void k_mstep_scalars_mca(int D, int H, const double* __restrict__ sca
   theta_new[1] = sqrt(fmax(scal[3] / (N * D), 0.0));
 }
 
+// DSC prior (the maximiser of sum_v vcount_v log pv_v on the simplex, with
+// N H latents in all): pv_v = vcount_v / (N H) for v >= 1, pv_0 the rest.
+__global__ void k_mstep_dsc_prior(int H, int nv, const double* __restrict__ scal,
+                                  const double* __restrict__ vcount,
+                                  double* __restrict__ theta_new) {
+  if (threadIdx.x || blockIdx.x) return;
+  const double NH = scal[4] * (double)H;
+  double rest = 1.0;
+  for (int v = 1; v < nv; ++v) {
+    const double pv = vcount[v] / NH;
+    theta_new[2 + v] = pv;
+    rest -= pv;
+  }
+  theta_new[2] = rest;
+}
+
+hipError_t launch_mstep_dsc_prior(int H, int nv, const double* scal, const double* vcount,
+                                  double* theta_new, hipStream_t st) {
+  hipLaunchKernelGGL(k_mstep_dsc_prior, dim3(1), dim3(64), 0, st, H, nv, scal, vcount,
+                     theta_new);
+  return hipGetLastError();
+}
+
 size_t mstep_workspace_bytes(int model, int D, int H) {
   if (is_max_model(model)) return 256;
   return 256 + round_up((size_t)H * H * 8, 256) + 2 * dinv_bytes(H) + round_up((size_t)D * 8, 256);

@@ -14,25 +14,54 @@ namespace prosper {
 // M-step); also clears the running max of the projection-row norms, the
 // redo-list counter of the unrolled state walk and the counter of points the
 // projection hands to the deferred exact selection.
+// DSC: the prior pv from the host values or from theta_dev[2 ..], and the
+// per-value constants of the walk and of the selection score.
 __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
                         const double* __restrict__ theta_dev, Theta* __restrict__ th,
                         float* __restrict__ pnorm, int32_t* __restrict__ redo_count,
-                        int32_t* __restrict__ defer_count, float beta) {
+                        int32_t* __restrict__ defer_count, float beta, DscParams dsc) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double pi = theta_dev ? theta_dev[0] : pi_h;
   double sigma = theta_dev ? theta_dev[1] : sigma_h;
   const double LOG2E = 1.4426950408889634;
   Theta t;
-  t.pi = pi;
   t.sigma = sigma;
-  t.c0 = (double)H * log1p(-pi) - 0.5 * (double)D * log(2.0 * M_PI * sigma * sigma);
+  const double lgauss = 0.5 * (double)D * log(2.0 * M_PI * sigma * sigma);
   double lam = 1.0 / (2.0 * sigma * sigma);
   t.lam = (float)lam;
   t.lam2 = (float)(lam * LOG2E);
-  double c1 = (model == PROSPER_TSC) ? log(pi / (2.0 * (1.0 - pi))) : log(pi / (1.0 - pi));
-  t.c1_2 = (float)(c1 * LOG2E);
   t.ln2 = (float)0.6931471805599453;
   t.beta = beta;
+  t.nv = 0;
+  t.phimax = 0.0f;
+  t.csmax = 0.0f;
+  for (int v = 0; v < DSC_MAXV; ++v) {
+    t.phi[v] = 0.0f;
+    t.u2[v] = 0.0f;
+    t.cs[v] = 0.0f;
+    t.csd[v] = 0.0;
+  }
+  if (model == PROSPER_DSC) {
+    const double p0 = theta_dev ? theta_dev[2] : dsc.pv[0];
+    t.nv = dsc.nv;
+    pi = 1.0 - p0;
+    for (int v = 1; v < dsc.nv; ++v) {
+      const double lr = log((theta_dev ? theta_dev[2 + v] : dsc.pv[v]) / p0);
+      t.phi[v] = dsc.phi[v];
+      t.u2[v] = (float)(lr * LOG2E);
+      t.csd[v] = sigma * sigma * lr;
+      t.cs[v] = (float)t.csd[v];
+      t.phimax = fmaxf(t.phimax, fabsf(dsc.phi[v]));
+      t.csmax = fmaxf(t.csmax, fabsf(t.cs[v]));
+    }
+    t.c0 = (double)H * log(p0) - lgauss;
+    t.c1_2 = 0.0f;
+  } else {
+    t.c0 = (double)H * log1p(-pi) - lgauss;
+    double c1 = (model == PROSPER_TSC) ? log(pi / (2.0 * (1.0 - pi))) : log(pi / (1.0 - pi));
+    t.c1_2 = (float)(c1 * LOG2E);
+  }
+  t.pi = pi;
   *th = t;
   *pnorm = 0.0f;
   if (redo_count) *redo_count = 0;
@@ -147,9 +176,10 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
 // before k_norms on the same stream.
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
-                             hipStream_t st, int32_t* defer_count, float beta) {
+                             hipStream_t st, int32_t* defer_count, float beta,
+                             const DscParams& dsc) {
   hipLaunchKernelGGL(k_theta, dim3(1), dim3(64), 0, st, model, D, H, pi, sigma, theta_dev,
-                     p.theta, p.pnorm, redo_count, defer_count, beta);
+                     p.theta, p.pnorm, redo_count, defer_count, beta, dsc);
   return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@
 // log-joint up to latent-independent terms and the positive factor 1/sigma^2:
 //   r_h = b_h - 1/2 ||P_h||^2           (BSC, MCA)
 //   r_h = |b_h| - 1/2 ||P_h||^2         (TSC: better of the two signs)
+//   r_h = max_v cs_v + phi_v b_h - phi_v^2 1/2 ||P_h||^2   (DSC: best value)
+// (score modes of k_select.hpp; DSC always takes the exact path)
 //
 // Selection is exact with respect to the real-valued scores: the projection
 // error is bounded by delta (the FP32 summation bound plus, for the BF16
@@ -73,7 +75,8 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
     const float* __restrict__ hn_lo, const float* __restrict__ pnorm, int Hp, int score_abs,
     float kappa, int32_t* __restrict__ sel, float* __restrict__ bc, float* __restrict__ yy_out,
     uint8_t* __restrict__ flagged, double* __restrict__ scal, int tile_bytes,
-    float* __restrict__ defer, int defer_cap, int32_t* __restrict__ defer_count) {
+    float* __restrict__ defer, int defer_cap, int32_t* __restrict__ defer_count,
+    const Theta* __restrict__ th) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float yyS[TM];
   __shared__ double yydS[TM];
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
       const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
       exact_select_point<RM>(Bs + r * Hs, lane, R, H, Hp, score_abs, true, sl.thr[r],
                              sl.thrN[r], delta, Y + n * D, D, Dp, Pt32, hn_hi, hn_lo,
-                             sel + n * Hp, bc + n * Hp, flagged ? flagged + n : nullptr);
+                             sel + n * Hp, bc + n * Hp, flagged ? flagged + n : nullptr, th);
       if (lane == 0) yy_out[n] = yyS[r];
     }
   } else {
@@ -459,10 +462,10 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
       const int64_t n = n0 + r;
       if (n >= N) break;
       const float ynorm = sqrtf(yyS[r]);
-      const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+      const float delta = select_delta(score_abs, th, kappa, ynorm, pn);
       exact_select_point<RM>(Bs + r * Hs, lane, R, H, Hp, score_abs, false, 0.0f, 0.0f, delta,
                              Y + n * D, D, Dp, Pt32, hn_hi, hn_lo, sel + n * Hp, bc + n * Hp,
-                             flagged ? flagged + n : nullptr);
+                             flagged ? flagged + n : nullptr, th);
       if (lane == 0) yy_out[n] = yyS[r];
     }
   }
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(256) void k_select_deferred(
     const int64_t n = *reinterpret_cast<const int64_t*>(ent);
     exact_select_point<RM>(ent + 8, lane, R, H, Hp, score_abs, true, ent[2], ent[3], ent[4],
                            Y + n * D, D, Dp, Pt32, hn_hi, hn_lo, sel + n * Hp, bc + n * Hp,
-                           flagged ? flagged + n : nullptr);
+                           flagged ? flagged + n : nullptr, nullptr);
   }
 }
 
@@ -512,7 +515,7 @@ static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(256), lds, st, Y, N, D, Dp, H, p.Pt32,
                      p.Pt_hi, p.Pt_lo, p.hn_hi, p.hn_lo, p.pnorm, Hp, score_abs, kappa, s.sel,
                      s.bc, s.yy, flagged, scal, tile_bytes, s.defer, FAST ? s.defer_cap : 0,
-                     s.defer_count);
+                     s.defer_count, p.theta);
   if (FAST && s.defer_cap > 0) {
     // at most one wave per entry; 1024 workgroups are what stays resident at
     // this kernel's register count (4 waves per SIMD)
@@ -556,7 +559,8 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
                                  int H, int Hp, const Prepared& p, const Scratch& s,
                                  uint8_t* flagged, double* scal, hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  const int score_abs = (model == PROSPER_TSC) ? 1 : 0;
+  const int score_abs =
+      (model == PROSPER_TSC) ? SCORE_ABS : (model == PROSPER_DSC ? SCORE_DSC : SCORE_LIN);
   // Bound on |computed b - exact b| per unit of ||y|| ||P_h|| (Cauchy-Schwarz
   // on sum |y_d P_hd|).  FP32: every product rounded once, at most D + 1
   // roundings along the FP32 accumulation (padding adds exact zeros).  BF16
@@ -574,7 +578,8 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
   const size_t lds = project_lds_bytes(Dp, H, prec, tm);
   const int Hpad = round_up(H, 64);
   const bool small = Hpad <= 256;
-  const bool fast = Hp <= FAST_HP && Hp < H;
+  // the lane-per-point pass ranks by the BSC/TSC/MCA score forms only
+  const bool fast = Hp <= FAST_HP && Hp < H && model != PROSPER_DSC;
 #define PS_CASE(P, T, R)                                                                       \
   return fast ? launch_ps<P, T, R, true>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged,  \
                                          scal, lds, st)                                        \

@@ -105,6 +105,58 @@ __device__ __forceinline__ int wave_sum_rows(double (&v)[RPW], int lane, double&
   return row;
 }
 
+// Score modes of the selection: the singleton log-joint of latent h up to
+// latent-independent terms and the factor 1/sigma^2, from b_h and the half
+// norm hn_h = 1/2 ||P_h||^2:
+//   SCORE_LIN  b - hn                      (BSC, MCA, MMCA)
+//   SCORE_ABS  |b| - hn                    (TSC: the better sign)
+//   SCORE_DSC  max_{v >= 1} cs_v + phi_v b - phi_v^2 hn
+//              (DSC: the best non-zero value, cs_v = sigma^2 ln(pv_v/pv_0))
+enum { SCORE_LIN = 0, SCORE_ABS = 1, SCORE_DSC = 2 };
+
+__device__ __forceinline__ float dsc_score(const Theta* __restrict__ th, float b, float hnh,
+                                           float hnl) {
+  const int nv = th->nv;
+  const float hn = hnh + hnl;
+  float r = -INFINITY;
+#pragma unroll
+  for (int v = 1; v < DSC_MAXV; ++v) {
+    if (v < nv) {
+      const float ph = th->phi[v];
+      r = fmaxf(r, (th->cs[v] + ph * b) - (ph * ph) * hn);
+    }
+  }
+  return r;
+}
+
+// The same from a (near-exact) b and hn in FP64, rounded once.
+__device__ __forceinline__ float dsc_score_d(const Theta* __restrict__ th, double b, double hn) {
+  const int nv = th->nv;
+  double r = -INFINITY;
+#pragma unroll
+  for (int v = 1; v < DSC_MAXV; ++v) {
+    if (v < nv) {
+      const double ph = (double)th->phi[v];
+      r = fmax(r, (th->csd[v] + ph * b) - (ph * ph) * hn);
+    }
+  }
+  return (float)r;
+}
+
+// Bound on |computed score - real score| given the bound kappa ||y|| ||P_h||
+// on the projection error of b: the score is Lipschitz in b with constant
+// max |phi_v| (1 for BSC/TSC/MCA), plus the FP32 roundings of the score's
+// own arithmetic (about 2 units of 2^-24 of its terms for b - hn, 4 for the
+// DSC form with its constant, product and square).
+__device__ __forceinline__ float select_delta(int smode, const Theta* __restrict__ th,
+                                              float kappa, float ynorm, float pn) {
+  if (smode == SCORE_DSC) {
+    const float pm = th->phimax;
+    return pm * kappa * ynorm * pn + 2.4e-7f * (pm * ynorm * pn + pm * pm * pn * pn + th->csmax);
+  }
+  return kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+}
+
 // Exact selection of one point by one wave from its score row (lane l holds
 // the latents 64 i + l).  cH and cN are the H'-th and (H'+1)-th largest
 // computed scores: given by the caller (have_thr), else found by a radix
@@ -117,12 +169,13 @@ __device__ __forceinline__ int wave_sum_rows(double (&v)[RPW], int lane, double&
 // are within 1e-6 max(1, |r|).
 template <int RM>
 __device__ __forceinline__ void exact_select_point(const float* __restrict__ brow, int lane, int R, int H, int Hp,
-                                   int score_abs, bool have_thr, float cH, float cN, float delta,
+                                   int smode, bool have_thr, float cH, float cN, float delta,
                                    const float* __restrict__ yrow, int D, int Dp,
                                    const float* __restrict__ Pt32,
                                    const float* __restrict__ hn_hi,
                                    const float* __restrict__ hn_lo, int32_t* __restrict__ selp,
-                                   float* __restrict__ bcp, uint8_t* flagp) {
+                                   float* __restrict__ bcp, uint8_t* flagp,
+                                   const Theta* __restrict__ th) {
   float b[RM], sc[RM];
   uint32_t key[RM];
 #pragma unroll
@@ -130,8 +183,15 @@ __device__ __forceinline__ void exact_select_point(const float* __restrict__ bro
     const int h = 64 * i + lane;
     const bool valid = (i < R) && (h < H);
     b[i] = (i < R) ? brow[h] : 0.0f;
-    const float bb = score_abs ? fabsf(b[i]) : b[i];
-    sc[i] = valid ? (bb - hn_hi[h < H ? h : 0]) - hn_lo[h < H ? h : 0] : 0.0f;
+    const int hh = h < H ? h : 0;
+    float s0;
+    if (smode == SCORE_DSC) {
+      s0 = dsc_score(th, b[i], hn_hi[hh], hn_lo[hh]);
+    } else {
+      const float bb = smode == SCORE_ABS ? fabsf(b[i]) : b[i];
+      s0 = (bb - hn_hi[hh]) - hn_lo[hh];
+    }
+    sc[i] = valid ? s0 : 0.0f;
     key[i] = valid ? f2key(sc[i]) : 0u;
   }
   uint64_t selm[RM];
@@ -229,8 +289,13 @@ __device__ __forceinline__ void exact_select_point(const float* __restrict__ bro
               c = c + co + e2;
             }
             const int h = hs[m];
-            const float sg = (score_abs && s < 0.0f) ? -1.0f : 1.0f;
-            const float rr = (sg * s - hn_hi[h]) + (sg * c - hn_lo[h]);
+            float rr;
+            if (smode == SCORE_DSC) {
+              rr = dsc_score_d(th, (double)s + (double)c, (double)hn_hi[h] + (double)hn_lo[h]);
+            } else {
+              const float sg = (smode == SCORE_ABS && s < 0.0f) ? -1.0f : 1.0f;
+              rr = (sg * s - hn_hi[h]) + (sg * c - hn_lo[h]);
+            }
             const int i = h >> 6, l2 = h & 63;
 #pragma unroll
             for (int i2 = 0; i2 < RM; ++i2) {

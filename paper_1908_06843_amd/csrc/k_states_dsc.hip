@@ -1,0 +1,268 @@
+// State walk for discrete sparse coding (DSC: latents take one of V values
+// phi_0 = 0, phi_1, ..., phi_{V-1} with a categorical prior, linear
+// superposition and Gaussian noise; Table 1).
+//
+// Relative to the zero state and in log2 units the log-joint of a state of
+// K_n with actives j (slots of the preselection, c_j = I_n(j)) at values
+// v_j splits into singleton and pair terms of the candidates, as for BSC
+// and TSC, now with the value of each active entering both:
+//   lj(s) = sum_j u_{v_j}(j) + sum_{j<j'} phi_{v_j} phi_{v_j'} g(j, j'),
+//   u_v(j) = log2(pv_v/pv_0) + lam2 (2 phi_v b_cj - phi_v^2 G_cjcj),
+//   g(j, j') = -2 lam2 G_cjcj'
+// (Eq. 1 categorical prior, Eq. 2 with f = W s; b = W^T y, G = W^T W).
+//
+// One wave per data point, lanes stride over the state table (act: active
+// slot mask; code: the 3-bit value codes of the actives, lowest slot first).
+// Pass 1 finds the maximum and the lanes' top lists, pass 2 accumulates the
+// weights per (value, slot) and per slot pair in LDS; the moments follow:
+//   <s_j> = sum_v phi_v Q_v(j) / Z,  <s_j^2> = sum_v phi_v^2 Q_v(j) / Z,
+//   <#latents at phi_v> = sum_j Q_v(j) / Z,  <s_j s_j'> = P(j, j') / Z.
+#include "dev_common.hpp"
+#include "prosper_internal.hpp"
+
+namespace prosper {
+
+namespace {
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+struct DscLds {
+  float u[DSC_MAXV][32];  // singleton terms per value (row 0 unused)
+  float g[32 * 32];       // pair base terms, i < j
+  float Q[DSC_MAXV][32];  // weight of the states with slot j at value v
+  float P[32 * 32];       // sum of weight * phi_i phi_j, i < j
+  float phi[DSC_MAXV];
+};
+
+// Log-joint (relative, log2) of one state from the LDS terms.
+__device__ __forceinline__ float dsc_state_lj(const DscLds& S, uint32_t act, uint32_t code) {
+  float L = 0.0f;
+  uint32_t rem = act, cw = code;
+  while (rem) {
+    const int j = __ffs(rem) - 1;
+    rem &= rem - 1u;
+    const int cj = (int)(cw & 7u);
+    cw >>= 3;
+    L += S.u[cj][j];
+    const float pj = S.phi[cj];
+    uint32_t pre = act & ((1u << j) - 1u), ci_w = code;
+    while (pre) {
+      const int i = __ffs(pre) - 1;
+      pre &= pre - 1u;
+      const int ci = (int)(ci_w & 7u);
+      ci_w >>= 3;
+      L += (S.phi[ci] * pj) * S.g[i * 32 + j];
+    }
+  }
+  return L;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_states_dsc(
+    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
+    const float* __restrict__ G, int H, int64_t N, int Hp, int64_t nstates,
+    const uint32_t* __restrict__ tab_act, const uint32_t* __restrict__ tab_code,
+    const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
+    uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk,
+    float* __restrict__ ss_out, double* __restrict__ vcount, double* __restrict__ scal) {
+  __shared__ DscLds sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  DscLds& S = sh[wave];
+  const float lam2 = th->lam2;
+  const int nv = th->nv;
+  const float beta = th->beta;
+  const bool tempered = beta != 1.0f;
+  double acc_k = 0.0, acc_l = 0.0, acc_v = 0.0;  // acc_v: value `lane` (1 <= lane < nv)
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < N; base += (int64_t)gridDim.x * 4) {
+    const bool live = base + wave < N;
+    const int64_t n = live ? base + wave : 0;
+    if (live) {
+      if (lane < DSC_MAXV) S.phi[lane] = lane < nv ? th->phi[lane] : 0.0f;
+      for (int j = lane; j < Hp; j += 64) {
+        const int sj = sel[n * Hp + j];
+        const float gjj = G[(int64_t)sj * H + sj];
+        const float bj = bc[n * Hp + j];
+        for (int v = 0; v < DSC_MAXV; ++v) {
+          const float ph = th->phi[v];
+          S.u[v][j] = (v >= 1 && v < nv) ? th->u2[v] + lam2 * (2.0f * ph * bj - ph * ph * gjj)
+                                         : 0.0f;
+          S.Q[v][j] = 0.0f;
+        }
+      }
+      for (int idx = lane; idx < Hp * Hp; idx += 64) {
+        const int i = idx / Hp, j = idx % Hp;
+        if (i < j) {
+          S.g[i * 32 + j] = -2.0f * lam2 * G[(int64_t)sel[n * Hp + i] * H + sel[n * Hp + j]];
+          S.P[i * 32 + j] = 0.0f;
+        }
+      }
+    }
+    __syncthreads();
+    // pass 1: max and the lane's top list (states visited in increasing index)
+    float mx = -INFINITY;
+    float tv[PROSPER_MAX_TOPK];
+    int ti[PROSPER_MAX_TOPK];
+#pragma unroll
+    for (int t = 0; t < PROSPER_MAX_TOPK; ++t) {
+      tv[t] = -INFINITY;
+      ti[t] = 0x7fffffff;
+    }
+    if (live) {
+      for (int64_t k = lane; k < nstates; k += 64) {
+        const float L = dsc_state_lj(S, tab_act[k], tab_code[k]);
+        mx = fmaxf(mx, L);
+        if (topk > 0) {
+          float v = L;
+          int id = (int)k;
+#pragma unroll
+          for (int t = 0; t < PROSPER_MAX_TOPK; ++t) {
+            const bool better = v > tv[t];
+            const float v2 = better ? tv[t] : v;
+            const int i2 = better ? ti[t] : id;
+            tv[t] = better ? v : tv[t];
+            ti[t] = better ? id : ti[t];
+            v = v2;
+            id = i2;
+          }
+        }
+      }
+    }
+    const float m = wave_max(mx);
+    // pass 2: weights into the (value, slot) and pair accumulators
+    float z = 0.0f, z1 = 0.0f;
+    if (live) {
+      for (int64_t k = lane; k < nstates; k += 64) {
+        const uint32_t act = tab_act[k], code = tab_code[k];
+        const float L = dsc_state_lj(S, act, code);
+        const float e1 = exp2_fast(L - m);
+        const float e = tempered ? exp2_fast(beta * (L - m)) : e1;
+        z += e;
+        z1 += e1;
+        uint32_t rem = act, cw = code;
+        while (rem) {
+          const int j = __ffs(rem) - 1;
+          rem &= rem - 1u;
+          const int cj = (int)(cw & 7u);
+          cw >>= 3;
+          atomicAdd(&S.Q[cj][j], e);
+          const float ej = e * S.phi[cj];
+          uint32_t pre = act & ((1u << j) - 1u), ci_w = code;
+          while (pre) {
+            const int i = __ffs(pre) - 1;
+            pre &= pre - 1u;
+            const int ci = (int)(ci_w & 7u);
+            ci_w >>= 3;
+            atomicAdd(&S.P[i * 32 + j], ej * S.phi[ci]);
+          }
+        }
+      }
+    }
+    const float Z = wave_sum(z);
+    const float Z1 = tempered ? wave_sum(z1) : Z;
+    __syncthreads();
+    if (live) {
+      const float invZ = 1.0f / Z;
+      const double lL = th->c0 - (double)th->lam * (double)yy[n] +
+                        0.6931471805599453 * ((double)m + (double)log2f(Z1));
+      for (int j = lane; j < Hp; j += 64) {
+        float m1 = 0.0f, m2 = 0.0f;
+        for (int v = 1; v < nv; ++v) {
+          const float q = S.Q[v][j];
+          m1 += S.phi[v] * q;
+          m2 += S.phi[v] * S.phi[v] * q;
+        }
+        s_mean[n * Hp + j] = m1 * invZ;
+        if (ss_out) ss_out[(int64_t)j * N + n] = m2 * invZ;
+      }
+      if (ss_out) {  // pairs i < j in row-major order after the diagonal
+        for (int idx = lane; idx < Hp * Hp; idx += 64) {
+          const int i = idx / Hp, j = idx % Hp;
+          if (i < j) {
+            const int p = Hp + i * (2 * Hp - i - 1) / 2 + (j - i - 1);
+            ss_out[(int64_t)p * N + n] = S.P[i * 32 + j] * invZ;
+          }
+        }
+      }
+      // expected number of latents at each value: lane v sums Q_v over the slots
+      float vm = 0.0f;
+      if (lane >= 1 && lane < nv)
+        for (int j = 0; j < Hp; ++j) vm += S.Q[lane][j];
+      vm *= invZ;
+      const float kmean = wave_sum(vm);
+      acc_v += vm;
+      if (lane == 0) {
+        if (logL) logL[n] = (float)lL;
+        acc_k += kmean;
+        acc_l += lL;
+      }
+      // top-k merge: repeated wave arg-max over the lanes' list heads
+      for (int t = 0; t < topk; ++t) {
+        float v = tv[0];
+        int id = ti[0];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const float v2 = __shfl_xor(v, o, 64);
+          const int i2 = __shfl_xor(id, o, 64);
+          const bool take = (v2 > v) || (v2 == v && i2 < id);
+          v = take ? v2 : v;
+          id = take ? i2 : id;
+        }
+        if (ti[0] == id) {  // the winner pops its head
+#pragma unroll
+          for (int s2 = 0; s2 + 1 < PROSPER_MAX_TOPK; ++s2) {
+            tv[s2] = tv[s2 + 1];
+            ti[s2] = ti[s2 + 1];
+          }
+          tv[PROSPER_MAX_TOPK - 1] = -INFINITY;
+          ti[PROSPER_MAX_TOPK - 1] = 0x7fffffff;
+        }
+        if (lane == 0) {
+          if (top_q) top_q[n * topk + t] = exp2_fast((tempered ? beta : 1.0f) * (v - m)) * invZ;
+          if (top_mask) {
+            // active mask and the three bit planes of the value codes (a
+            // list entry never filled, possible only with NaN log-joints,
+            // reads state 0)
+            const int64_t ids = (id >= 0 && (int64_t)id < nstates) ? id : 0;
+            const uint32_t act = tab_act[ids];
+            uint32_t cw = tab_code[ids], rem = act, p0 = 0u, p1 = 0u, p2 = 0u;
+            while (rem) {
+              const int j = __ffs(rem) - 1;
+              rem &= rem - 1u;
+              p0 |= (cw & 1u) << j;
+              p1 |= ((cw >> 1) & 1u) << j;
+              p2 |= ((cw >> 2) & 1u) << j;
+              cw >>= 3;
+            }
+            uint32_t* o = top_mask + (n * topk + t) * 4;
+            o[0] = act;
+            o[1] = p0;
+            o[2] = p1;
+            o[3] = p2;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (scal && lane == 0) {
+    atomicAdd(&scal[0], acc_k);
+    atomicAdd(&scal[1], acc_l);
+  }
+  if (vcount && lane >= 1 && lane < nv) atomicAdd(&vcount[lane], acc_v);
+}
+
+hipError_t launch_states_dsc(int Hp, int64_t N, int H, int64_t nstates, const uint32_t* tab_act,
+                             const uint32_t* tab_code, const Prepared& p, const Scratch& s,
+                             float* logL, uint32_t* top_mask, float* top_q, int topk, bool acc,
+                             double* vcount, double* scal, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  int64_t blocks = (N + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_states_dsc, dim3((unsigned)blocks), dim3(256), 0, st, s.sel, s.bc, s.yy,
+                     p.G, H, N, Hp, nstates, tab_act, tab_code, p.theta, s.s_mean, logL,
+                     top_mask, top_q, topk, acc ? s.ss : nullptr, acc ? vcount : nullptr, scal);
+  return hipGetLastError();
+}
+
+}  // namespace prosper

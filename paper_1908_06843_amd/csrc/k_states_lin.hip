@@ -226,11 +226,13 @@ __global__ __launch_bounds__(256) void k_states_generic(
         if (lane == 0) {
           if (top_q) top_q[n * topk + t] = fast_exp2((tempered ? beta : 1.0f) * (v - m)) * invZ;
           if (top_mask) {
+            // a list entry never filled (only with NaN log-joints) reads state 0
+            const int64_t ids = (id >= 0 && (int64_t)id < nstates) ? id : 0;
             if (TSC) {
-              top_mask[(n * topk + t) * 2 + 0] = tab_act[id];
-              top_mask[(n * topk + t) * 2 + 1] = tab_sgn[id];
+              top_mask[(n * topk + t) * 2 + 0] = tab_act[ids];
+              top_mask[(n * topk + t) * 2 + 1] = tab_sgn[ids];
             } else {
-              top_mask[n * topk + t] = tab_act[id];
+              top_mask[n * topk + t] = tab_act[ids];
             }
           }
         }
@@ -262,7 +264,9 @@ PROSPER_TREE_SHAPES(X)
 
 bool has_tree_kernel(int model, int Hp, int gamma) {
 #define X(T, HP, GM) \
-  if ((model == PROSPER_TSC) == T && !is_max_model(model) && Hp == HP && gamma == GM) return true;
+  if ((model == PROSPER_TSC) == T && (model == PROSPER_BSC || model == PROSPER_TSC) && \
+      Hp == HP && gamma == GM)                                                            \
+    return true;
   PROSPER_TREE_SHAPES(X)
 #undef X
   return false;

@@ -50,22 +50,27 @@ __device__ __forceinline__ uint64_t binom_dev(int n, int k) {
 
 // State t of the canonical order: number of actives k ascending, then the
 // lexicographic rank of the slot tuple among the k-subsets of the H' slots,
-// then (TSC) the sign code counting up, bit i of the code giving the sign of
-// the i-th active slot (set = -1).
-__global__ __launch_bounds__(256) void k_build_table(int tsc, int Hp, int gamma, int64_t ns,
-                                                     uint32_t* __restrict__ act,
+// then the value code of the support counting up in base `radix` (1: BSC,
+// MCA, MMCA; 2: TSC; V-1: DSC): TSC bit i of the code is the sign of the
+// i-th active slot (set = -1, stored as a mask); DSC digit i plus one is the
+// value code of the i-th active slot (stored in bits 3i .. 3i+2).
+__global__ __launch_bounds__(256) void k_build_table(int radix, int dsc, int Hp, int gamma,
+                                                     int64_t ns, uint32_t* __restrict__ act,
                                                      uint32_t* __restrict__ sgn) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= ns) return;
   int64_t r = t;
   int k = 0;
+  int64_t pw = 1;  // radix^k
   for (; k <= gamma; ++k) {
-    const int64_t cnt = (int64_t)binom_dev(Hp, k) << (tsc ? k : 0);
+    const int64_t cnt = (int64_t)binom_dev(Hp, k) * pw;
     if (r < cnt) break;
     r -= cnt;
+    pw *= radix;
   }
-  const uint32_t code = tsc ? (uint32_t)(r & ((1ll << k) - 1)) : 0u;
-  uint64_t comb = tsc ? (uint64_t)(r >> k) : (uint64_t)r;
+  const uint64_t code = (uint64_t)(r % pw);
+  uint64_t comb = (uint64_t)(r / pw);
+  uint64_t digits = code;
   uint32_t a = 0u, s = 0u;
   int x = 0;
   for (int i = 0; i < k; ++i) {
@@ -76,18 +81,22 @@ __global__ __launch_bounds__(256) void k_build_table(int tsc, int Hp, int gamma,
       ++x;
     }
     a |= 1u << x;
-    if ((code >> i) & 1u) s |= 1u << x;
+    const uint32_t dg = (uint32_t)(digits % (uint64_t)radix);
+    digits /= (uint64_t)radix;
+    if (dsc) s |= (1u + dg) << (3 * i);
+    else if (dg) s |= 1u << x;
     ++x;
   }
   act[t] = a;
   sgn[t] = s;
 }
 
-static hipError_t launch_build_table(int model, int Hp, int gamma, int64_t ns, uint32_t* act,
-                              uint32_t* sgn, hipStream_t st) {
+static hipError_t launch_build_table(int model, int nv, int Hp, int gamma, int64_t ns,
+                                     uint32_t* act, uint32_t* sgn, hipStream_t st) {
   if (ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_table, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st,
-                     model == PROSPER_TSC ? 1 : 0, Hp, gamma, ns, act, sgn);
+  const int radix = model == PROSPER_TSC ? 2 : (model == PROSPER_DSC ? nv - 1 : 1);
+  hipLaunchKernelGGL(k_build_table, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, radix,
+                     model == PROSPER_DSC ? 1 : 0, Hp, gamma, ns, act, sgn);
   return hipGetLastError();
 }
 
@@ -146,8 +155,8 @@ prosper_status prosper_estep_static(const prosper_args* a, const float* Y, const
   Prepared p = carve_prep(base + 2 * tab_b, Dp, H, a->precision);
   Scratch sc = carve_estep(base + fixed, L, a, out);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  e = launch_build_table(is_max_model(a->model) ? PROSPER_BSC : a->model, Hp, a->gamma, ns, act,
-                         sgn, s);
+  e = launch_build_table(is_max_model(a->model) ? PROSPER_BSC : a->model, a->nvalues, Hp,
+                         a->gamma, ns, act, sgn, s);
   if (e == hipSuccess)
     e = enqueue_estep(nullptr, a, Y, W, out, acc, s, p, sc, act, sgn, ns, ncu_s, StatsHook(), 0);
   if (e != hipSuccess) return hip_error(e, "E-step launch");

@@ -26,6 +26,11 @@ typedef __bf16 bf16;
 // with c1 = log(pi/(1-pi)) (BSC, MCA) or log(pi/(2(1-pi))) (TSC),
 // lam = 1/(2 sigma^2) and c0 = H log(1-pi) - D/2 log(2 pi sigma^2)
 // (Eq. 1 prior, Eq. 2 Gaussian noise).
+// DSC (discrete values phi_v, prior pv_v): the singleton term of value v is
+//   u_v = log2(pv_v/pv_0) + lam2 (2 phi_v b - phi_v^2 G_hh),
+// the pair term of values v, v' is -2 lam2 phi_v phi_v' G_hh', and
+// c0 = H log(pv_0) - D/2 log(2 pi sigma^2).
+static constexpr int DSC_MAXV = PROSPER_MAX_VALUES;
 struct Theta {
   double pi, sigma;
   double c0;     // natural log
@@ -34,7 +39,32 @@ struct Theta {
   float c1_2;    // c1 * log2(e)
   float ln2;     // log(2)
   float beta;    // posterior temperature (1 = none)
+  // DSC only (nv = 0 for the other models)
+  int nv;                  // V
+  float phi[DSC_MAXV];     // phi_v
+  float u2[DSC_MAXV];      // log2(pv_v / pv_0)
+  float cs[DSC_MAXV];      // sigma^2 ln(pv_v / pv_0): constant of the selection score
+  double csd[DSC_MAXV];    // the same in FP64 (band re-scoring)
+  float phimax, csmax;     // max_v |phi_v|, max_v |cs_v| (v >= 1; selection error bound)
 };
+
+// The DSC value set and prior of an argument block (host values).
+struct DscParams {
+  int nv = 0;
+  float phi[DSC_MAXV] = {};
+  double pv[DSC_MAXV] = {};
+};
+inline DscParams dsc_params(const prosper_args* a) {
+  DscParams d;
+  if (a->model == PROSPER_DSC) {
+    d.nv = a->nvalues;
+    for (int v = 0; v < DSC_MAXV; ++v) {
+      d.phi[v] = a->phi[v];
+      d.pv[v] = a->pv[v];
+    }
+  }
+  return d;
+}
 
 // The posterior temperature of an argument block (0 stands for 1).
 inline float args_beta(const prosper_args* a) { return a->beta == 0.0f ? 1.0f : a->beta; }
@@ -109,17 +139,19 @@ struct Carve {
 };
 
 // Host-side helpers shared by the ABI and the serving runtime.
+// nv: the DSC value count (ignored by the other models).
 void build_table(int model, int Hp, int gamma, std::vector<uint32_t>& act,
-                 std::vector<uint32_t>& sgn);
+                 std::vector<uint32_t>& sgn, int nv = 0);
 prosper_status count_states(int32_t model, int32_t Hp, int32_t gamma, int64_t* out,
-                            std::string* msg);
+                            std::string* msg, int nv = 0);
 size_t prep_bytes(int Dp, int H, int prec);
 Prepared carve_prep(void* base, int Dp, int H, int prec);
 
 // Launchers (each returns the first HIP error it sees).
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
-                             hipStream_t st, int32_t* defer_count = nullptr, float beta = 1.0f);
+                             hipStream_t st, int32_t* defer_count = nullptr, float beta = 1.0f,
+                             const DscParams& dsc = DscParams());
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
                        const Prepared& p, hipStream_t st);
 // Entries of the projection's deferral list for N points: enough for a
@@ -143,6 +175,13 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
                              hipStream_t st, float beta = 1.0f);
 // Max-superposition models: MCA and MMCA share the walk, statistics and M-step.
 inline bool is_max_model(int m) { return m == PROSPER_MCA || m == PROSPER_MMCA; }
+// DSC state walk (table-driven; tab_code: 3-bit value codes of the actives).
+// With acc, writes pair-major <s s^T> into s.ss for the statistics kernel and
+// adds the expected value counts into vcount.
+hipError_t launch_states_dsc(int Hp, int64_t N, int H, int64_t nstates, const uint32_t* tab_act,
+                             const uint32_t* tab_code, const Prepared& p, const Scratch& s,
+                             float* logL, uint32_t* top_mask, float* top_q, int topk, bool acc,
+                             double* vcount, double* scal, hipStream_t st);
 // MCA/MMCA state walk (max / largest-magnitude superposition).
 hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
                              const uint32_t* tab_act, const float* Y, const Prepared& p,
@@ -163,7 +202,10 @@ size_t mstep_workspace_bytes(int model, int D, int H);
 hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
                         const double* scal, const float* W_old, float* W_new,
                         double* theta_new, void* work, hipStream_t st);
-// The two halves of launch_mstep for BSC/TSC: factorisation of B into the
+// DSC prior update after the linear M-step: theta_new[2 + v] = pv_v.
+hipError_t launch_mstep_dsc_prior(int H, int nv, const double* scal, const double* vcount,
+                                  double* theta_new, hipStream_t st);
+// The two halves of launch_mstep for BSC/TSC/DSC: factorisation of B into the
 // workspace, and the solve + parameter update that uses it.
 hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* work,
                                hipStream_t st);

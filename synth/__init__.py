@@ -19,9 +19,9 @@ import numpy as np
 
 __all__ = [
     "rng", "bars_dictionary", "unit_norm_gaussian_dictionary",
-    "abs_gaussian_dictionary", "sample_binary", "sample_ternary",
+    "abs_gaussian_dictionary", "sample_binary", "sample_ternary", "sample_discrete",
     "linear_observations", "max_observations", "Workload", "WORKLOADS",
-    "make_workload", "initial_params", "serving_requests",
+    "make_workload", "initial_params", "initial_dsc_prior", "serving_requests",
 ]
 
 
@@ -76,6 +76,12 @@ def sample_ternary(g: np.random.Generator, N: int, H: int, pi: float) -> np.ndar
     return s
 
 
+def sample_discrete(g: np.random.Generator, N: int, H: int, phi, pv) -> np.ndarray:
+    """s_h = phi_v with probability pv_v, independently (DSC categorical prior)."""
+    codes = g.choice(len(phi), size=(N, H), p=np.asarray(pv, dtype=np.float64))
+    return np.asarray(phi, dtype=np.float64)[codes]
+
+
 def linear_observations(g: np.random.Generator, W: np.ndarray, S: np.ndarray,
                         sigma: float) -> np.ndarray:
     """y = W s + sigma * eps, eps ~ N(0, I)  (linear superposition)."""
@@ -111,6 +117,8 @@ class Workload:
     init_seed: int
     iters: int = 1
     note: str = ""
+    phi: Tuple[float, ...] = ()   # DSC value set (phi_0 = 0)
+    pv: Tuple[float, ...] = ()    # DSC prior over the values
 
 
 WORKLOADS = {
@@ -124,6 +132,9 @@ WORKLOADS = {
                     "ternary latents, Gaussian unit-norm dictionary"),
     "serve": Workload("serve", "bsc", 256, 512, 0, 6.0 / 512, 0.5, 12, 5, 4, 104, 0,
                       "resident dictionary for E-step-only serving"),
+    "dsc": Workload("dsc", "dsc", 144, 100, 100000, 0.04, 1.0, 8, 3, 5, 105, 1,
+                    "discrete latents in {0, 1, -1, 2, -2}, Gaussian unit-norm dictionary",
+                    phi=(0.0, 1.0, -1.0, 2.0, -2.0), pv=(0.96, 0.015, 0.015, 0.005, 0.005)),
 }
 
 
@@ -145,6 +156,8 @@ def make_workload(name: str, N: Optional[int] = None, seed: Optional[int] = None
         W = unit_norm_gaussian_dictionary(g, wl.D, wl.H)
     if wl.model == "tsc":
         S = sample_ternary(g, N, wl.H, wl.pi)
+    elif wl.model == "dsc":
+        S = sample_discrete(g, N, wl.H, wl.phi, wl.pv)
     else:
         S = sample_binary(g, N, wl.H, wl.pi)
     if wl.model == "mca":
@@ -158,7 +171,9 @@ def initial_params(wl: Workload, Y: np.ndarray, seed: Optional[int] = None):
     """Learning-run initialisation: W0, pi0 = 1/H, sigma0 = std of all of Y.
 
     Bars: W0 ~ N(0, 1).  Other workloads: W0 ~ N(0, 1/D); MCA takes |.| so the
-    initial components are nonnegative like the generating ones.
+    initial components are nonnegative like the generating ones.  DSC starts
+    its prior at pv_0 = 1 - 1/H with the rest spread evenly (see
+    initial_dsc_prior).
     """
     g = rng(wl.init_seed if seed is None else seed)
     if wl.name == "bars":
@@ -170,6 +185,12 @@ def initial_params(wl: Workload, Y: np.ndarray, seed: Optional[int] = None):
     pi0 = 1.0 / wl.H
     sigma0 = float(np.asarray(Y, dtype=np.float64).std())
     return W0.astype(np.float32), pi0, sigma0
+
+
+def initial_dsc_prior(wl: Workload) -> Tuple[float, ...]:
+    """pv_0 = 1 - 1/H, the other V - 1 values 1/(H (V - 1)) each."""
+    V = len(wl.phi)
+    return (1.0 - 1.0 / wl.H,) + (1.0 / (wl.H * (V - 1)),) * (V - 1)
 
 
 def serving_requests(n_requests: int, seed: int = 4, max_patches: int = 4096,

@@ -138,3 +138,82 @@ def test_null_arguments_are_rejected():
     assert lib.prosper_serve_stop(None) == -1
     assert lib.prosper_serve_wait(None, 1, 0, None) == -1
     assert lib.prosper_ctx_create(0, 0, None) == -1
+
+
+# ---------------------------------------------------------------- DSC
+def oracle_dsc_words(V, Hp, gamma):
+    """The oracle's DSC table as (active mask, packed 3-bit codes)."""
+    act, codes = [], []
+    for slots, cds in O.dsc_state_table(V, Hp, gamma):
+        a = 0
+        w = 0
+        for i, (j, c) in enumerate(zip(slots, cds)):
+            a |= 1 << j
+            w |= c << (3 * i)
+        act.append(a)
+        codes.append(w)
+    return np.array(act, dtype=np.uint32), np.array(codes, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("V,Hp,gamma", [(2, 8, 3), (3, 8, 3), (4, 8, 3), (5, 6, 4), (8, 5, 2),
+                                        (4, 10, 0), (3, 4, 4), (4, 12, 3)])
+def test_dsc_state_table_matches_oracle_bit_exactly(V, Hp, gamma):
+    act, codes = _lib.dsc_state_table(V, Hp, gamma)
+    oact, ocodes = oracle_dsc_words(V, Hp, gamma)
+    assert _lib.dsc_state_count(V, Hp, gamma) == O.dsc_state_count(V, Hp, gamma) == len(oact)
+    np.testing.assert_array_equal(act, oact)
+    np.testing.assert_array_equal(codes, ocodes)
+
+
+def test_dsc_v3_table_is_the_tsc_table():
+    """Codes 1, 2 of V = 3 are TSC's +1, -1: the tables agree state for state."""
+    act, codes = _lib.dsc_state_table(3, 8, 3)
+    tact, tsgn = _lib.state_table("tsc", 8, 3)
+    np.testing.assert_array_equal(act, tact)
+    neg = np.zeros_like(tsgn)
+    for k, (a, w) in enumerate(zip(act, codes)):
+        i, m = 0, int(a)
+        while m:
+            j = (m & -m).bit_length() - 1
+            if (int(w) >> (3 * i)) & 7 == 2:
+                neg[k] |= 1 << j
+            m &= m - 1
+            i += 1
+    np.testing.assert_array_equal(neg, tsgn)
+
+
+def test_dsc_state_count_limits():
+    with pytest.raises(_lib.ProsperError):
+        _lib.dsc_state_count(1, 8, 3)
+    with pytest.raises(_lib.ProsperError):
+        _lib.dsc_state_count(9, 8, 3)
+    with pytest.raises(_lib.ProsperError):
+        _lib.dsc_state_count(2, 12, 11)       # gamma above the 3-bit code word
+    with pytest.raises(_lib.ProsperError):
+        _lib.dsc_state_count(8, 20, 8)        # beyond PROSPER_MAX_STATES
+
+
+def dsc_args(**kw):
+    d = dict(model="dsc", precision="fp32", N=10, D=16, H=8, Hprime=4, gamma=2, pi=0.0,
+             sigma=0.5, phi=(0.0, 1.0, -1.0, 2.0), pv=(0.7, 0.1, 0.1, 0.1))
+    d.update(kw)
+    return _lib.make_args(**d)
+
+
+def test_dsc_validate():
+    assert _lib.validate(dsc_args()) == 0
+    assert _lib.validate(dsc_args(accumulate=1, flags=_lib.FLAG_FACTOR_B)) == 0
+    # device-side prior: host pv not inspected
+    assert _lib.validate(dsc_args(pv=(0.0, 0.0, 0.0, 0.0), theta_dev=0x1000)) == 0
+    for bad in [dict(phi=(1.0, 2.0), pv=(0.5, 0.5)),             # phi_0 != 0
+                dict(phi=(0.0, 1.0, 1.0), pv=(0.5, 0.25, 0.25)),  # repeated value
+                dict(phi=(0.0, 0.0), pv=(0.5, 0.5)),              # zero as a non-zero value
+                dict(phi=(0.0, float("inf")), pv=(0.5, 0.5)),
+                dict(phi=(0.0,), pv=(1.0,)),                      # V < 2
+                dict(pv=(0.7, 0.1, 0.1, 0.2)),                    # sum != 1
+                dict(pv=(0.8, 0.3, -0.2, 0.1)),                   # negative
+                dict(gamma=3, Hprime=12, H=16, phi=tuple(range(8)),
+                     pv=(0.3,) + (0.1,) * 7)]:                    # |K| fine, checks pass
+        a = dsc_args(**bad)
+        want = 0 if "gamma" in bad else -1
+        assert _lib.validate(a) == want, bad
