@@ -54,6 +54,27 @@ def state_walk_ops(Hp: int, gamma: int, model: str = "bsc") -> int:
     return ops
 
 
+def dsc_walk_ops(Hp: int, gamma: int, V: int) -> int:
+    """Algorithmic VALU op slots per point of the DSC walk, priced like the
+    BSC/TSC walk (each state's log-joint from its parent's).  Per non-zero
+    state: the value term c_v + phi_v (b_j + f_j - phi_v g_j) and the add to
+    the parent's log-joint (3), the weight (1 sub + 4 for the
+    transcendental), the subtree sum into the parent (1), <s_j> (2: phi_v T
+    and its add), <s_j^2> (1), <s_i s_j> for the k-1 earlier slots (k-1),
+    the value count (1).  Per state below depth 1: one entry of its parent's
+    field vector, shared by the V-1 values of the state's slot (1/(V-1)).
+    Pivot walk over the states with <= 2 actives: log-joint (3) and max (1)."""
+    ops = 0.0
+    for k in range(1, gamma + 1):
+        c = math.comb(Hp, k) * (V - 1) ** k
+        ops += c * (3 + 5 + 1 + 2 + 1 + (k - 1) + 1)
+        if k >= 2:
+            ops += c / (V - 1)
+        if k <= 2:
+            ops += c * 4
+    return int(ops)
+
+
 CPU_SHARE = 16  # host CPU share of one GPU on the benchmark machines
 
 
@@ -78,14 +99,15 @@ def cpu_workers() -> int:
     return max(1, min(CPU_SHARE, avail))
 
 
-def cpu_oracle_baseline(model, Y, W, pi, sigma, Hp, gamma, target_s, seed=11):
-    """Time the FP64 oracle on a bounded sample with a process pool."""
+def cpu_oracle_baseline(model, Y, W, pi, sigma, Hp, gamma, target_s, seed=11, dsc=None):
+    """Time the FP64 oracle on a bounded sample with a process pool (DSC:
+    dsc = (phi, pv), pi unused)."""
     import concurrent.futures as cf
     import numpy as np
     from oracle import prosper_oracle as O
     cores = cpu_workers()
     t0 = time.perf_counter()
-    O.estep(model, Y[:8], W, pi, sigma, Hp, gamma)
+    _oracle_chunk((model, Y[:8], W, pi, sigma, Hp, gamma, dsc))
     per_pt = (time.perf_counter() - t0) / 8
     n = int(max(cores * 8, min(Y.shape[0], target_s * cores / max(per_pt, 1e-6) / 1.5)))
     n = min(n, Y.shape[0])
@@ -94,7 +116,7 @@ def cpu_oracle_baseline(model, Y, W, pi, sigma, Hp, gamma, target_s, seed=11):
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=cores, initializer=_one_thread) as ex:
         parts = list(ex.map(_oracle_chunk,
-                            [(model, Y[c], W, pi, sigma, Hp, gamma) for c in chunks]))
+                            [(model, Y[c], W, pi, sigma, Hp, gamma, dsc) for c in chunks]))
     wall = time.perf_counter() - t0
     ref = {k: np.concatenate([p[k] for p in parts]) for k in ("sel", "s_mean", "logL", "flagged")}
     return idx, ref, wall, cores
@@ -112,8 +134,11 @@ def _one_thread():
 
 def _oracle_chunk(a):
     from oracle import prosper_oracle as O
-    model, Yc, W, pi, sigma, Hp, gamma = a
-    r = O.estep(model, Yc, W, pi, sigma, Hp, gamma)
+    model, Yc, W, pi, sigma, Hp, gamma, dsc = a
+    if model == "dsc":
+        r = O.dsc_estep(Yc, W, dsc[0], dsc[1], sigma, Hp, gamma)
+    else:
+        r = O.estep(model, Yc, W, pi, sigma, Hp, gamma)
     return {k: r[k] for k in ("sel", "s_mean", "logL", "flagged")}
 
 
@@ -135,13 +160,14 @@ def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
     """Warm up, then time `steps` EM iterations; returns (ms/step, profile)."""
     Wd = W0.clone()
     theta = theta0.clone()
-    acc = api.new_acc(wl.model, wl.D, wl.H)
-    factor_b = wl.model in ("bsc", "tsc")
+    acc = api.new_acc(wl.model, wl.D, wl.H, nvalues=len(wl.phi))
+    factor_b = wl.model in ("bsc", "tsc", "dsc")
+    phi = wl.phi if wl.model == "dsc" else None
 
     def step():
         api.zero_acc(acc)
         api.estep(Yd, Wd, Hprime=wl.Hprime, gamma=wl.gamma, model=wl.model, precision=prec,
-                  theta=theta, acc=acc, want=(), ctx=ctx, factor_b=factor_b)
+                  theta=theta, acc=acc, want=(), ctx=ctx, factor_b=factor_b, phi=phi)
         api.mstep(acc, Wd, model=wl.model, W_new=Wd, theta_new=theta, ctx=ctx)
 
     for _ in range(warmup):
@@ -269,19 +295,23 @@ def side_workload(name, np, torch, api, ctx, steps, warmup, cpu_s, no_cpu):
     wl = synth.WORKLOADS[name]
     Y, _, _, _ = synth.make_workload(name)
     W0, pi0, s0 = synth.initial_params(wl, Y)
-    K = api.state_count(wl.model, wl.Hprime, wl.gamma)
+    dsc = wl.model == "dsc"
+    pv0 = synth.initial_dsc_prior(wl) if dsc else ()
+    K = (api.dsc_state_count(len(wl.phi), wl.Hprime, wl.gamma) if dsc
+         else api.state_count(wl.model, wl.Hprime, wl.gamma))
     dev = torch.device("cuda", 0)
     Yd = torch.tensor(Y, device=dev)
     W0d = torch.tensor(W0, device=dev)
-    theta0 = torch.tensor([pi0, s0], dtype=torch.float64, device=dev)
+    theta0 = torch.tensor([pi0, s0, *pv0], dtype=torch.float64, device=dev)
     prec = "fp32" if wl.model in ("mca", "mmca") else "bf16"
     ms, wall_ms, prof, _, _ = run_em_steps(api, torch, Yd, W0d, theta0, wl, prec, steps,
                                            warmup, ctx)
     N = Y.shape[0]
     dom = max((k for k in prof if not k.startswith("mstep")), key=lambda k: prof[k]["ms"])
     roof = roofline(dom, prof[dom]["ms"] / prof[dom]["launches"] * 1e-3, N, wl)
+    vals = f" V={len(wl.phi)} phi={list(wl.phi)}" if dsc else ""
     rec = {"workload": f"{wl.model.upper()} {name}: D={wl.D} H={wl.H} N={N} H'={wl.Hprime} "
-                       f"gamma={wl.gamma} |K|={K}, one EM iteration",
+                       f"gamma={wl.gamma}{vals} |K|={K}, one EM iteration",
            "metric": "truncated E-step joint evals/s", "value": N * K / (ms * 1e-3),
            "unit": "joint evals/s", "ms_per_step": ms, "wall_ms_per_step": wall_ms,
            "dtype": "bf16" if prec == "bf16" else "f32",
@@ -289,14 +319,16 @@ def side_workload(name, np, torch, api, ctx, steps, warmup, cpu_s, no_cpu):
            "roofline": roof, "cpu_baseline": None, "error_vs_fp64_oracle": None}
     if not no_cpu:
         idx, ref, wall, cores = cpu_oracle_baseline(wl.model, Y, W0, pi0, s0, wl.Hprime,
-                                                    wl.gamma, cpu_s)
+                                                    wl.gamma, cpu_s,
+                                                    dsc=(wl.phi, pv0) if dsc else None)
         rec["cpu_baseline"] = {
             "value": len(idx) * K / wall, "unit": "joint evals/s", "cores": cores,
             "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{len(idx)} of {N} points (seeded), full E-step per point, "
                       f"{wall:.1f} s wall on {cores} processes x 1 BLAS thread"}
         out = api.estep(Yd, W0d, pi0, s0, Hprime=wl.Hprime, gamma=wl.gamma, model=wl.model,
-                        precision=prec, ctx=ctx)
+                        precision=prec, ctx=ctx, phi=wl.phi if dsc else None,
+                        pv=pv0 if dsc else None)
         torch.cuda.synchronize()
         g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
         rec["error_vs_fp64_oracle"] = error_stats(g, ref)
@@ -328,6 +360,10 @@ def roofline(kernel, per_launch_s, N, wl):
                     "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s"}
     elif kernel == "states_lin":
         work = N * state_walk_ops(wl.Hprime, wl.gamma, wl.model)
+        roof = {"bound": "alu", "achieved": work / per_launch_s / 1e12,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
+    elif kernel == "states_dsc":
+        work = N * dsc_walk_ops(wl.Hprime, wl.gamma, len(wl.phi))
         roof = {"bound": "alu", "achieved": work / per_launch_s / 1e12,
                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s"}
     elif kernel == "states_max":
@@ -383,7 +419,7 @@ def pmc_pass():
     """Short run for hardware-counter passes: one device copy of a known size
     (the scale reference for the byte counters), two BF16 E-steps with
     statistics at BSC scale, then one E-step with statistics on each of the
-    MCA and TSC workloads."""
+    MCA, TSC and DSC workloads."""
     import torch
     import synth
     from paper_1908_06843_amd import api
@@ -412,6 +448,14 @@ def pmc_pass():
         api.estep(torch.tensor(Y2, device=dev), torch.tensor(W2, device=dev), p2, s2,
                   Hprime=w2.Hprime, gamma=w2.gamma, model=w2.model, precision=prec, acc=acc2,
                   want=(), ctx=ctx)
+    # and one on the DSC workload
+    w3 = synth.WORKLOADS["dsc"]
+    Y3, _, _, _ = synth.make_workload("dsc")
+    W3, _, s3 = synth.initial_params(w3, Y3)
+    acc3 = api.new_acc("dsc", w3.D, w3.H, nvalues=len(w3.phi))
+    api.estep(torch.tensor(Y3, device=dev), torch.tensor(W3, device=dev), sigma=s3,
+              Hprime=w3.Hprime, gamma=w3.gamma, model="dsc", precision="bf16", acc=acc3,
+              want=(), ctx=ctx, phi=w3.phi, pv=synth.initial_dsc_prior(w3))
     torch.cuda.synchronize()
     print(json.dumps({"pmc_pass": "done", "copy_bytes": int(Yd.numel() * 4),
                       "project_select_source_hash": kernel_source_hash("project_select")}),
@@ -428,7 +472,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--no-side", action="store_true",
-                    help="skip the MCA, TSC and bars workloads")
+                    help="skip the MCA, TSC, bars and DSC workloads")
     ap.add_argument("--side-steps", type=int, default=10)
     ap.add_argument("--side-cpu-seconds", type=float, default=6.0)
     ap.add_argument("--no-fp32", action="store_true")
@@ -496,7 +540,7 @@ def main():
     if not args.no_side:
         side = {name: side_workload(name, np, torch, api, ctx, args.side_steps, 2,
                                     args.side_cpu_seconds, args.no_cpu)
-                for name in ("mca", "tsc", "bars")}
+                for name in ("mca", "tsc", "bars", "dsc")}
     serving = None
     if not args.no_serve:
         serving = {p: serving_bench(np, api, args.serve_requests, p) for p in ("bf16", "fp32")}

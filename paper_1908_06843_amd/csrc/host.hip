@@ -590,9 +590,9 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
     e = timed(c, is_max_model(model) ? "states_max"
                  : (model == PROSPER_DSC ? "states_dsc" : "states_lin"), s, [&] {
       if (model == PROSPER_DSC)
-        return launch_states_dsc(Hp, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask, top_q,
-                                 a->topk, Aacc != nullptr, Aacc ? acc->vcount : nullptr, scal,
-                                 s);
+        return launch_states_dsc(Hp, a->gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL,
+                                 top_mask, top_q, a->topk, Aacc != nullptr,
+                                 Aacc ? acc->vcount : nullptr, scal, s, args_beta(a));
       if (is_max_model(model))
         return launch_states_max(model, Hp, a->gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL,
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);

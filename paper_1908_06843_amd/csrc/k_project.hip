@@ -8,7 +8,7 @@
 //   r_h = b_h - 1/2 ||P_h||^2           (BSC, MCA)
 //   r_h = |b_h| - 1/2 ||P_h||^2         (TSC: better of the two signs)
 //   r_h = max_v cs_v + phi_v b_h - phi_v^2 1/2 ||P_h||^2   (DSC: best value)
-// (score modes of k_select.hpp; DSC always takes the exact path)
+// (score modes of k_select.hpp; the error bound delta of each in select_delta)
 //
 // Selection is exact with respect to the real-valued scores: the projection
 // error is bounded by delta (the FP32 summation bound plus, for the BF16
@@ -67,7 +67,20 @@ struct SelLds {
 //      k_select_deferred when the caller gives a deferral list with room
 //      (the b row and the thresholds are written out), else here.
 //      Without FAST every point takes the exact path here.
-template <int PREC, int TM, int RM, bool FAST>
+// Ranking score of latent h in the lane-per-point pass: the BSC/TSC/MCA
+// forms as written there, or the DSC score of k_select.hpp.
+template <bool DSC>
+__device__ __forceinline__ float fast_score(float bv, int score_abs, float hh, float hl,
+                                            const Theta* __restrict__ th) {
+  if constexpr (DSC) {
+    return dsc_score(th, bv, hh, hl);
+  } else {
+    const float bb = score_abs ? fabsf(bv) : bv;
+    return (bb - hh) - hl;
+  }
+}
+
+template <int PREC, int TM, int RM, bool FAST, bool DSC = false>
 __global__ __launch_bounds__(256, 2) void k_project_select(
     const float* __restrict__ Y, int64_t N, int D, int Dp, int H,
     const float* __restrict__ Pt32, const bf16* __restrict__ Pt_hi,
@@ -348,8 +361,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
 #pragma unroll 8
     for (int h = hq0; h < hq1; ++h) {
       const float bv = brow[h];
-      const float bb = score_abs ? fabsf(bv) : bv;
-      list_insert<FAST_KL>(tl, (bb - hnS[h]) - hnS[Hpad + h]);
+      list_insert<FAST_KL>(tl, fast_score<DSC>(bv, score_abs, hnS[h], hnS[Hpad + h], th));
     }
     if (wave > 0 && plane) {
 #pragma unroll
@@ -366,7 +378,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
       const bool valid = plane && n < N;
       const float cH = list_at<FAST_KL>(tl, Hp - 1), cN = list_at<FAST_KL>(tl, Hp);
       const float ynorm = sqrtf(valid ? yyS[p] : 0.0f);
-      const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+      const float delta = select_delta(score_abs, th, kappa, ynorm, pn);
       const float gap = cH - cN;
       const bool fast =
           valid && gap - 2.0f * delta > 1e-6f * fmaxf(1.0f, fabsf(cH) + 2.0f * delta);
@@ -383,14 +395,12 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
     // ---- 4c. each quarter lists its latents at or above the threshold
     if (plane) {
       const bool f = sl.fast[p] != 0;
-      const float th = sl.thr[p];
+      const float thr = sl.thr[p];
       int cnt = 0;
 #pragma unroll 8
       for (int h = hq0; h < hq1; ++h) {
-        const float bv = brow[h];
-        const float bb = score_abs ? fabsf(bv) : bv;
-        const float v = (bb - hnS[h]) - hnS[Hpad + h];
-        if (f && v >= th && cnt < FAST_HP) {
+        const float v = fast_score<DSC>(brow[h], score_abs, hnS[h], hnS[Hpad + h], th);
+        if (f && v >= thr && cnt < FAST_HP) {
           sl.u.qsel[wave][p][cnt] = (uint16_t)h;
           ++cnt;
         }
@@ -436,7 +446,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
         const int64_t n = n0 + r;
         float* ent = defer + (int64_t)(dbase + i) * Hrow;
         const float ynorm = sqrtf(yyS[r]);
-        const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+        const float delta = select_delta(score_abs, th, kappa, ynorm, pn);
         for (int h = lane; h < Hpad; h += 64) ent[8 + h] = Bs[r * Hs + h];
         if (lane == 0) {
           *reinterpret_cast<int64_t*>(ent) = n;
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
       const int r = sl.slow[i];
       const int64_t n = n0 + r;
       const float ynorm = sqrtf(yyS[r]);
-      const float delta = kappa * ynorm * pn + 1.2e-7f * (ynorm * pn + pn * pn);
+      const float delta = select_delta(score_abs, th, kappa, ynorm, pn);
       exact_select_point<RM>(Bs + r * Hs, lane, R, H, Hp, score_abs, true, sl.thr[r],
                              sl.thrN[r], delta, Y + n * D, D, Dp, Pt32, hn_hi, hn_lo,
                              sel + n * Hp, bc + n * Hp, flagged ? flagged + n : nullptr, th);
@@ -487,7 +497,8 @@ __global__ __launch_bounds__(256) void k_select_deferred(
     const float* __restrict__ defer, int defer_cap, const int32_t* __restrict__ defer_count,
     const float* __restrict__ Y, int D, int Dp, int H, int Hp, const float* __restrict__ Pt32,
     const float* __restrict__ hn_hi, const float* __restrict__ hn_lo, int score_abs,
-    int32_t* __restrict__ sel, float* __restrict__ bc, uint8_t* __restrict__ flagged) {
+    int32_t* __restrict__ sel, float* __restrict__ bc, uint8_t* __restrict__ flagged,
+    const Theta* __restrict__ th) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cnt = min(*defer_count, defer_cap);
@@ -499,15 +510,15 @@ __global__ __launch_bounds__(256) void k_select_deferred(
     const int64_t n = *reinterpret_cast<const int64_t*>(ent);
     exact_select_point<RM>(ent + 8, lane, R, H, Hp, score_abs, true, ent[2], ent[3], ent[4],
                            Y + n * D, D, Dp, Pt32, hn_hi, hn_lo, sel + n * Hp, bc + n * Hp,
-                           flagged ? flagged + n : nullptr, nullptr);
+                           flagged ? flagged + n : nullptr, th);
   }
 }
 
-template <int PREC, int TM, int RM, bool FAST>
+template <int PREC, int TM, int RM, bool FAST, bool DSC = false>
 static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int Hp,
                             int score_abs, float kappa, const Prepared& p, const Scratch& s,
                             uint8_t* flagged, double* scal, size_t lds, hipStream_t st) {
-  auto kern = k_project_select<PREC, TM, RM, FAST>;
+  auto kern = k_project_select<PREC, TM, RM, FAST, DSC>;
   hipError_t e0 = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
   if (e0 != hipSuccess) return e0;
   const int64_t nblk = (N + TM - 1) / TM;
@@ -522,7 +533,7 @@ static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int
     const int nwg = (int)std::min<int64_t>(1024, ((int64_t)s.defer_cap + 3) / 4);
     hipLaunchKernelGGL(k_select_deferred<RM>, dim3((unsigned)nwg), dim3(256), 0, st, s.defer,
                        s.defer_cap, s.defer_count, Y, D, Dp, H, Hp, p.Pt32, p.hn_hi, p.hn_lo,
-                       score_abs, s.sel, s.bc, flagged);
+                       score_abs, s.sel, s.bc, flagged, p.theta);
   }
   return hipGetLastError();
 }
@@ -578,13 +589,29 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
   const size_t lds = project_lds_bytes(Dp, H, prec, tm);
   const int Hpad = round_up(H, 64);
   const bool small = Hpad <= 256;
-  // the lane-per-point pass ranks by the BSC/TSC/MCA score forms only
-  const bool fast = Hp <= FAST_HP && Hp < H && model != PROSPER_DSC;
+  const bool fast = Hp <= FAST_HP && Hp < H;
+  // DSC: its own lane-per-point pass for H <= 256 (the exact path otherwise)
+  const bool dsc = model == PROSPER_DSC;
+  if (dsc && fast && small) {
+#define PS_DSC(P, T)                                                                        \
+  return launch_ps<P, T, 4, true, true>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged, \
+                                        scal, lds, st)
+    if (prec == PROSPER_FP32) {
+      if (tm == 64) PS_DSC(PROSPER_FP32, 64);
+      if (tm == 32) PS_DSC(PROSPER_FP32, 32);
+      PS_DSC(PROSPER_FP32, 16);
+    }
+    if (tm == 64) PS_DSC(PROSPER_BF16, 64);
+    if (tm == 32) PS_DSC(PROSPER_BF16, 32);
+    PS_DSC(PROSPER_BF16, 16);
+#undef PS_DSC
+  }
 #define PS_CASE(P, T, R)                                                                       \
-  return fast ? launch_ps<P, T, R, true>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged,  \
-                                         scal, lds, st)                                        \
-              : launch_ps<P, T, R, false>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged, \
-                                          scal, lds, st)
+  return (fast && !dsc)                                                                        \
+             ? launch_ps<P, T, R, true>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged,   \
+                                        scal, lds, st)                                         \
+             : launch_ps<P, T, R, false>(Y, N, D, Dp, H, Hp, score_abs, kappa, p, s, flagged,  \
+                                         scal, lds, st)
   if (prec == PROSPER_FP32) {
     if (small) {
       if (tm == 64) PS_CASE(PROSPER_FP32, 64, 4);

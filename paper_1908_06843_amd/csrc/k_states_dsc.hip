@@ -65,7 +65,8 @@ __global__ __launch_bounds__(256) void k_states_dsc(
     const uint32_t* __restrict__ tab_act, const uint32_t* __restrict__ tab_code,
     const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
     uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk,
-    float* __restrict__ ss_out, double* __restrict__ vcount, double* __restrict__ scal) {
+    float* __restrict__ ss_out, double* __restrict__ vcount, double* __restrict__ scal,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count) {
   __shared__ DscLds sh[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   DscLds& S = sh[wave];
@@ -74,9 +75,11 @@ __global__ __launch_bounds__(256) void k_states_dsc(
   const float beta = th->beta;
   const bool tempered = beta != 1.0f;
   double acc_k = 0.0, acc_l = 0.0, acc_v = 0.0;  // acc_v: value `lane` (1 <= lane < nv)
-  for (int64_t base = (int64_t)blockIdx.x * 4; base < N; base += (int64_t)gridDim.x * 4) {
-    const bool live = base + wave < N;
-    const int64_t n = live ? base + wave : 0;
+  // list mode: only the points named in list[0 .. *list_count)
+  const int64_t npts = list ? (int64_t)*list_count : N;
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < npts; base += (int64_t)gridDim.x * 4) {
+    const bool live = base + wave < npts;
+    const int64_t n = !live ? 0 : (list ? (int64_t)list[base + wave] : base + wave);
     if (live) {
       if (lane < DSC_MAXV) S.phi[lane] = lane < nv ? th->phi[lane] : 0.0f;
       for (int j = lane; j < Hp; j += 64) {
@@ -252,16 +255,280 @@ __global__ __launch_bounds__(256) void k_states_dsc(
   if (vcount && lane >= 1 && lane < nv) atomicAdd(&vcount[lane], acc_v);
 }
 
-hipError_t launch_states_dsc(int Hp, int64_t N, int H, int64_t nstates, const uint32_t* tab_act,
-                             const uint32_t* tab_code, const Prepared& p, const Scratch& s,
-                             float* logL, uint32_t* top_mask, float* top_q, int topk, bool acc,
-                             double* vcount, double* scal, hipStream_t st) {
+// ------------------------------------------------------------ compiled walk
+// One lane per data point; the subset tree of (H', gamma) unrolled at compile
+// time (children of a node add one slot after the node's last slot), the
+// values of each added slot a uniform loop over v = 1 .. V-1.  With
+// f_S[k] = sum_{i in S} phi_{v_i} p_ik (p_ik = -2 lam2 G_ik), the child
+// (S + j at v) has
+//   lj = lj(S) + c_v + phi_v (b2_j + f_S[j] - phi_v g_j),   b2_j = 2 lam2 b_j,
+//   g_j = lam2 G_jj,  c_v = log2(pv_v/pv_0),
+//   f_{S+j}[k] = f_S[k] + phi_v p_jk   (k > j).
+// T(node) = the summed weight 2^(lj - m) of the node's subtree; a state holds
+// slot j at value v exactly when its path passes the node that added (j, v):
+//   Q_v(j) = sum of T over the nodes adding (j, v), <s_j> Z = sum phi_v Q_v(j),
+//   <s_j^2> Z = sum phi_v^2 Q_v(j), <s_i s_j> Z = sum over nodes adding (j, v)
+//   below an ancestor (i, v_i) of phi_{v_i} phi_v T.
+template <int HP>
+struct DscCtx {
+  float b2[HP], g[HP];
+  float p[HP][HP];
+  float ph[DSC_MAXV], c[DSC_MAXV];  // value v and its prior constant (compile-time index)
+  const Theta* th;                  // the same for a runtime (uniform) index
+  int nv;
+};
+
+__device__ __forceinline__ void keep(float& x) { asm volatile("" : "+v"(x)); }
+
+// A node at DEPTH whose children are the last level (DEPTH + 1 == GAMMA)
+// unrolls the values of its children at compile time (guarded by v < V), so
+// every value-indexed operand is a register; the upper levels, a small share
+// of the states, loop over the values at run time with scalar loads.
+template <int HP, int GAMMA, unsigned PRE, int LAST, int DEPTH>
+struct DscTree {
+  static constexpr bool LEAVES = DEPTH + 1 >= GAMMA;
+
+  static __device__ __forceinline__ void walk1(const DscCtx<HP>& C, const float (&f)[HP],
+                                               float L, float& mx) {
+    static_for<LAST + 1, HP>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const float bj = C.b2[j] + f[j];
+      if constexpr (LEAVES) {
+        static_for<1, DSC_MAXV>([&](auto vc) {
+          constexpr int v = decltype(vc)::value;
+          if (v < C.nv) {
+            const float ph = C.ph[v];
+            mx = fmaxf(mx, L + (C.c[v] + ph * (bj - ph * C.g[j])));
+            keep(mx);
+          }
+        });
+      } else {
+        for (int v = 1; v < C.nv; ++v) {
+          const float ph = C.th->phi[v];
+          const float Lc = L + (C.th->u2[v] + ph * (bj - ph * C.g[j]));
+          mx = fmaxf(mx, Lc);
+          keep(mx);
+          if constexpr (j + 1 < HP) {
+            float fc[HP];
+            static_for<j + 1, HP>([&](auto kc) {
+              constexpr int k = decltype(kc)::value;
+              fc[k] = f[k] + ph * C.p[j][k];
+            });
+            DscTree<HP, GAMMA, PRE | (1u << j), j, DEPTH + 1>::walk1(C, fc, Lc, mx);
+          }
+        }
+      }
+    });
+  }
+
+  // Moments of the node (j, v) with subtree weight T; aph[d] = value of the
+  // prefix's d-th active.
+  template <int J>
+  static __device__ __forceinline__ void moments(float ph, float T, const float (&aph)[GAMMA + 1],
+                                                 float (&M)[HP], float (&K2)[HP],
+                                                 float (&P)[HP][HP]) {
+    const float pT = ph * T;
+    M[J] += pT;
+    K2[J] += ph * pT;
+    keep(M[J]);
+    keep(K2[J]);
+    static_for<0, J>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      if constexpr ((PRE >> i) & 1u) {
+        constexpr int d = __builtin_popcount(PRE & ((1u << i) - 1u));
+        P[i][J] += aph[d] * pT;
+        keep(P[i][J]);
+      }
+    });
+  }
+
+  // returns the summed weight of the children subtrees
+  static __device__ __forceinline__ float walk2(const DscCtx<HP>& C, const float (&f)[HP],
+                                                const float (&aph)[GAMMA + 1], float L, float m,
+                                                float (&M)[HP], float (&K2)[HP],
+                                                float (&P)[HP][HP], float (&VC)[DSC_MAXV]) {
+    float tot = 0.0f;
+    static_for<LAST + 1, HP>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if constexpr (LEAVES) {
+        const float bj = C.b2[j] + f[j];
+        static_for<1, DSC_MAXV>([&](auto vc) {
+          constexpr int v = decltype(vc)::value;
+          if (v < C.nv) {
+            const float ph = C.ph[v];
+            const float T = exp2_fast(L + (C.c[v] + ph * (bj - ph * C.g[j])) - m);
+            moments<j>(ph, T, aph, M, K2, P);
+            VC[v] += T;
+            keep(VC[v]);
+            tot += T;
+          }
+        });
+      }
+    });
+    if constexpr (!LEAVES) {
+      // values outermost: the children's weights at value v are summed over
+      // the slots first, and that sum enters VC[v] by selects (a runtime index
+      // into VC would put the array in scratch memory)
+      for (int v = 1; v < C.nv; ++v) {
+        const float ph = C.th->phi[v], cv = C.th->u2[v];
+        float tv = 0.0f;
+        static_for<LAST + 1, HP>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const float Lc = L + (cv + ph * ((C.b2[j] + f[j]) - ph * C.g[j]));
+          float T = exp2_fast(Lc - m);
+          if constexpr (j + 1 < HP) {
+            float fc[HP];
+            static_for<j + 1, HP>([&](auto kc) {
+              constexpr int k = decltype(kc)::value;
+              fc[k] = f[k] + ph * C.p[j][k];
+            });
+            float ac[GAMMA + 1];
+            static_for<0, DEPTH>([&](auto dc) {
+              constexpr int d = decltype(dc)::value;
+              ac[d] = aph[d];
+            });
+            ac[DEPTH] = ph;
+            T += DscTree<HP, GAMMA, PRE | (1u << j), j, DEPTH + 1>::walk2(C, fc, ac, Lc, m, M,
+                                                                          K2, P, VC);
+          }
+          moments<j>(ph, T, aph, M, K2, P);
+          tv += T;
+        });
+        static_for<1, DSC_MAXV>([&](auto vc) {
+          constexpr int vv = decltype(vc)::value;
+          VC[vv] += (v == vv) ? tv : 0.0f;
+          keep(VC[vv]);
+        });
+        tot += tv;
+      }
+    }
+    return tot;
+  }
+};
+
+// One lane per point, 64-lane workgroups.  Pivot m = the max over the states
+// with at most two actives (a lower bound of the max: those weights are <= 1
+// and Z >= 1); a point whose Z could have overflowed (>= 2^64) is handed to
+// the table-driven kernel through the redo list and written by it.
+template <int HP, int GAMMA>
+__global__ __launch_bounds__(64) void k_states_dsc_tree(
+    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
+    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
+    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ ss_out,
+    double* __restrict__ vcount, double* __restrict__ scal, int32_t* __restrict__ redo_list,
+    int32_t* __restrict__ redo_count) {
+  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool live = n < N;
+  const int64_t nn = live ? n : N - 1;
+  const float lam2 = th->lam2;
+  DscCtx<HP> C;
+  C.th = th;
+  C.nv = th->nv;
+#pragma unroll
+  for (int v = 0; v < DSC_MAXV; ++v) {
+    C.ph[v] = th->phi[v];
+    C.c[v] = th->u2[v];
+  }
+  int s[HP];
+#pragma unroll
+  for (int j = 0; j < HP; ++j) {
+    s[j] = sel[nn * HP + j];
+    C.b2[j] = 2.0f * lam2 * bc[nn * HP + j];
+    C.g[j] = lam2 * G[(int64_t)s[j] * H + s[j]];
+  }
+#pragma unroll
+  for (int i = 0; i < HP; ++i)
+#pragma unroll
+    for (int j = i + 1; j < HP; ++j) C.p[i][j] = -2.0f * lam2 * G[(int64_t)s[i] * H + s[j]];
+  float M[HP], K2[HP], P[HP][HP], VC[DSC_MAXV], f0[HP], a0[GAMMA + 1];
+#pragma unroll
+  for (int i = 0; i < HP; ++i) {
+    M[i] = 0.0f;
+    K2[i] = 0.0f;
+    f0[i] = 0.0f;
+#pragma unroll
+    for (int j = i + 1; j < HP; ++j) P[i][j] = 0.0f;
+  }
+#pragma unroll
+  for (int v = 0; v < DSC_MAXV; ++v) VC[v] = 0.0f;
+#pragma unroll
+  for (int d = 0; d <= GAMMA; ++d) a0[d] = 0.0f;
+  float m = 0.0f;  // the zero state has lj = 0
+  constexpr int GPIV = GAMMA < 2 ? GAMMA : 2;
+  DscTree<HP, GPIV, 0u, -1, 0>::walk1(C, f0, 0.0f, m);
+  const float Z = exp2_fast(-m) + DscTree<HP, GAMMA, 0u, -1, 0>::walk2(C, f0, a0, 0.0f, m, M, K2,
+                                                                        P, VC);
+  bool ok = live;
+  if (GAMMA > 2 && live && !(Z < 1.8446744e19f)) {
+    ok = false;
+    redo_list[atomicAdd(redo_count, 1)] = (int32_t)n;
+  }
+  const float invZ = 1.0f / Z;
+  const double lL = th->c0 - (double)th->lam * (double)yy[nn] +
+                    0.6931471805599453 * ((double)m + (double)log2f(Z));
+  float km = 0.0f;
+  if (ok) {
+    if (logL) logL[n] = (float)lL;
+#pragma unroll
+    for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = M[j] * invZ;
+    if (ss_out) {  // pair-major: diagonal first, then i < j row-major
+      int q = HP;
+#pragma unroll
+      for (int i = 0; i < HP; ++i) {
+        ss_out[(int64_t)i * N + n] = K2[i] * invZ;
+#pragma unroll
+        for (int j = i + 1; j < HP; ++j) ss_out[(int64_t)(q++) * N + n] = P[i][j] * invZ;
+      }
+    }
+#pragma unroll
+    for (int v = 1; v < DSC_MAXV; ++v) km += VC[v];
+  }
+  if (scal) {
+    double k0 = ok ? (double)(km * invZ) : 0.0, l0 = ok ? lL : 0.0;
+    k0 = wave_sum_d(k0);
+    l0 = wave_sum_d(l0);
+    if (threadIdx.x == 0) {
+      atomicAdd(&scal[0], k0);
+      atomicAdd(&scal[1], l0);
+    }
+  }
+  if (vcount) {
+#pragma unroll
+    for (int v = 1; v < DSC_MAXV; ++v) {
+      if (v < C.nv) {
+        const double t = wave_sum_d(ok ? (double)(VC[v] * invZ) : 0.0);
+        if (threadIdx.x == 0) atomicAdd(&vcount[v], t);
+      }
+    }
+  }
+}
+
+// Shapes with a compiled DSC walk (any V).
+static bool has_dsc_tree(int Hp, int gamma) { return Hp == 8 && gamma == 3; }
+
+hipError_t launch_states_dsc(int Hp, int gamma, int64_t N, int H, int64_t nstates,
+                             const uint32_t* tab_act, const uint32_t* tab_code, const Prepared& p,
+                             const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
+                             int topk, bool acc, double* vcount, double* scal, hipStream_t st,
+                             float beta) {
   if (N <= 0) return hipSuccess;
+  float* ss_out = acc ? s.ss : nullptr;
+  double* vc = acc ? vcount : nullptr;
+  if (topk == 0 && beta == 1.0f && has_dsc_tree(Hp, gamma)) {
+    hipLaunchKernelGGL((k_states_dsc_tree<8, 3>), dim3((unsigned)((N + 63) / 64)), dim3(64), 0,
+                       st, s.sel, s.bc, s.yy, p.G, H, N, p.theta, s.s_mean, logL, ss_out, vc,
+                       scal, s.redo_list, s.redo_count);
+    // points whose weights could overflow with the pivot: the table-driven kernel
+    hipLaunchKernelGGL(k_states_dsc, dim3(32), dim3(256), 0, st, s.sel, s.bc, s.yy, p.G, H, N,
+                       Hp, nstates, tab_act, tab_code, p.theta, s.s_mean, logL, top_mask, top_q,
+                       0, ss_out, vc, scal, s.redo_list, s.redo_count);
+    return hipGetLastError();
+  }
   int64_t blocks = (N + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_states_dsc, dim3((unsigned)blocks), dim3(256), 0, st, s.sel, s.bc, s.yy,
                      p.G, H, N, Hp, nstates, tab_act, tab_code, p.theta, s.s_mean, logL,
-                     top_mask, top_q, topk, acc ? s.ss : nullptr, acc ? vcount : nullptr, scal);
+                     top_mask, top_q, topk, ss_out, vc, scal, nullptr, nullptr);
   return hipGetLastError();
 }
 

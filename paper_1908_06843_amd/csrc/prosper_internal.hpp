@@ -175,13 +175,15 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
                              hipStream_t st, float beta = 1.0f);
 // Max-superposition models: MCA and MMCA share the walk, statistics and M-step.
 inline bool is_max_model(int m) { return m == PROSPER_MCA || m == PROSPER_MMCA; }
-// DSC state walk (table-driven; tab_code: 3-bit value codes of the actives).
-// With acc, writes pair-major <s s^T> into s.ss for the statistics kernel and
-// adds the expected value counts into vcount.
-hipError_t launch_states_dsc(int Hp, int64_t N, int H, int64_t nstates, const uint32_t* tab_act,
-                             const uint32_t* tab_code, const Prepared& p, const Scratch& s,
-                             float* logL, uint32_t* top_mask, float* top_q, int topk, bool acc,
-                             double* vcount, double* scal, hipStream_t st);
+// DSC state walk (tab_code: 3-bit value codes of the actives): compiled for
+// (H', gamma) = (8, 3) without top-k or annealing, else table-driven.  With
+// acc, writes pair-major <s s^T> into s.ss for the statistics kernel and adds
+// the expected value counts into vcount.
+hipError_t launch_states_dsc(int Hp, int gamma, int64_t N, int H, int64_t nstates,
+                             const uint32_t* tab_act, const uint32_t* tab_code, const Prepared& p,
+                             const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
+                             int topk, bool acc, double* vcount, double* scal, hipStream_t st,
+                             float beta);
 // MCA/MMCA state walk (max / largest-magnitude superposition).
 hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
                              const uint32_t* tab_act, const float* Y, const Prepared& p,

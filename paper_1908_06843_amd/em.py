@@ -28,8 +28,8 @@ import torch
 
 from . import api
 
-__all__ = ["Model", "BSC_ET", "TSC_ET", "MCA_ET", "MMCA_ET", "Annealing", "LinearAnnealing",
-           "EM"]
+__all__ = ["Model", "BSC_ET", "TSC_ET", "MCA_ET", "MMCA_ET", "DSC_ET", "Annealing",
+           "LinearAnnealing", "EM"]
 
 
 def _device_tensor(x, device) -> torch.Tensor:
@@ -69,6 +69,25 @@ class Model:
         sigma = float(torch.std(Y.double(), correction=0))
         return {"W": W.contiguous(), "pi": 1.0 / self.H, "sigma": sigma}
 
+    # the DSC subclass adds its value set and prior; these are the hooks
+    def _phi(self):
+        return None
+
+    def _pv(self, params: Dict):
+        return None
+
+    def _nvalues(self) -> int:
+        return 0
+
+    def _theta(self, params: Dict) -> List[float]:
+        return [float(params["pi"]), float(params["sigma"])]
+
+    def _params_from_theta(self, W, th) -> Dict:
+        return {"W": W, "pi": float(th[0]), "sigma": float(th[1])}
+
+    def _state_count(self) -> int:
+        return api.state_count(self.kind, self.Hprime, self.gamma)
+
     # ------------------------------------------------------------- inference
     def inference(self, anneal: "Annealing", params: Dict, Y, topk: int = 5,
                   beta: Optional[float] = None) -> Dict:
@@ -80,13 +99,25 @@ class Model:
         Yd = _device_tensor(Y, self.device)
         W = _device_tensor(params["W"], self.device)
         b = anneal.beta(anneal.iterations - 1) if beta is None else float(beta)
-        k = min(int(topk), api.state_count(self.kind, self.Hprime, self.gamma))
-        out = api.estep(Yd, W, float(params["pi"]), float(params["sigma"]), Hprime=self.Hprime,
-                        gamma=self.gamma, model=self.kind, precision=self.precision, topk=k,
-                        beta=b)
+        k = min(int(topk), self._state_count())
+        out = api.estep(Yd, W, float(params.get("pi", 0.5)), float(params["sigma"]),
+                        Hprime=self.Hprime, gamma=self.gamma, model=self.kind,
+                        precision=self.precision, topk=k, beta=b, phi=self._phi(),
+                        pv=self._pv(params))
         sel = out["sel"].long()
         N = sel.shape[0]
         slots = torch.arange(self.Hprime, device=sel.device)
+        if self.kind == "dsc":
+            # value codes from the three bit planes, then the values themselves
+            act = out["top_mask"][..., 0].long()
+            code = sum(((out["top_mask"][..., 1 + p].long()[..., None] >> slots) & 1) << p
+                       for p in range(3))
+            phi = torch.tensor(self._phi(), dtype=torch.float32, device=sel.device)
+            vals = phi[code] * ((act[..., None] >> slots) & 1)
+            s = torch.zeros((N, k, self.H), dtype=torch.float32, device=sel.device)
+            s.scatter_(2, sel[:, None, :].expand(N, k, self.Hprime), vals)
+            return {"s": s, "p": out["top_q"], "sel": out["sel"], "s_mean": out["s_mean"],
+                    "logL": out["logL"], "flagged": out["flagged"]}
         if self.kind == "tsc":
             act = out["top_mask"][..., 0].long()
             neg = out["top_mask"][..., 1].long()
@@ -122,6 +153,48 @@ class MMCA_ET(Model):
     """Max-magnitude superposition: the active component of largest
     magnitude at each pixel."""
     kind = "mmca"
+
+
+class DSC_ET(Model):
+    """Discrete sparse coding: each latent takes one of the values phi
+    (phi[0] = 0) with a learned categorical prior pv; linear superposition.
+    The parameters carry "pv" beside W and sigma ("pi" = 1 - pv[0])."""
+    kind = "dsc"
+
+    def __init__(self, D: int, H: int, Hprime: int, gamma: int, phi, precision: str = "bf16",
+                 device: Optional[int] = None):
+        super().__init__(D, H, Hprime, gamma, precision, device)
+        self.phi = tuple(float(x) for x in phi)
+        if len(self.phi) < 2 or self.phi[0] != 0.0:
+            raise ValueError("phi holds at least two values and phi[0] = 0")
+
+    def standard_init(self, data: Dict, seed: int = 0) -> Dict:
+        """As the other models, with pv_0 = 1 - 1/H and the rest of the
+        prior spread evenly over the non-zero values."""
+        p = super().standard_init(data, seed)
+        V = len(self.phi)
+        p["pv"] = (1.0 - 1.0 / self.H,) + (1.0 / (self.H * (V - 1)),) * (V - 1)
+        return p
+
+    def _phi(self):
+        return self.phi
+
+    def _pv(self, params: Dict):
+        return tuple(float(x) for x in params["pv"])
+
+    def _nvalues(self) -> int:
+        return len(self.phi)
+
+    def _theta(self, params: Dict) -> List[float]:
+        pv = self._pv(params)
+        return [1.0 - pv[0], float(params["sigma"]), *pv]
+
+    def _params_from_theta(self, W, th) -> Dict:
+        return {"W": W, "pi": float(th[0]), "sigma": float(th[1]),
+                "pv": tuple(float(x) for x in th[2:])}
+
+    def _state_count(self) -> int:
+        return api.dsc_state_count(len(self.phi), self.Hprime, self.gamma)
 
 
 class Annealing:
@@ -189,7 +262,8 @@ class EM:
 
     def run(self, data: Optional[Dict] = None, callback=None) -> Dict:
         """Runs the schedule; `callback(it, W, theta)` (device tensors, W the
-        new dictionary, theta = (pi, sigma)) is called after every M-step."""
+        new dictionary, theta = (pi, sigma), DSC: (pi, sigma, pv_0, ..)) is called
+        after every M-step."""
         m = self.model
         data = data if data is not None else self.data
         if data is None:
@@ -198,18 +272,17 @@ class EM:
         if self.lparams is None:
             self.lparams = m.standard_init({"y": Y})
         W = _device_tensor(self.lparams["W"], m.device).clone()
-        theta = torch.tensor([float(self.lparams["pi"]), float(self.lparams["sigma"])],
-                             dtype=torch.float64, device=m.device)
+        theta = torch.tensor(m._theta(self.lparams), dtype=torch.float64, device=m.device)
         ctx = api.context(m.device.index)
-        acc = api.new_acc(m.kind, m.D, m.H, device=m.device.index)
+        acc = api.new_acc(m.kind, m.D, m.H, device=m.device.index, nvalues=m._nvalues())
         W_next = torch.empty_like(W)
-        factor_b = m.kind in ("bsc", "tsc")
+        factor_b = m.kind in ("bsc", "tsc", "dsc")
         for it in range(self.anneal.iterations):
             beta = self.anneal.beta(it)
             api.zero_acc(acc)
             api.estep(Y, W, Hprime=m.Hprime, gamma=m.gamma, model=m.kind,
                       precision=m.precision, theta=theta, acc=acc, want=(), ctx=ctx,
-                      factor_b=factor_b, beta=beta)
+                      factor_b=factor_b, beta=beta, phi=m._phi())
             api.mstep(acc, W, model=m.kind, W_new=W_next, theta_new=theta, ctx=ctx)
             W, W_next = W_next, W
             eps = self.anneal.noise(it)
@@ -221,6 +294,5 @@ class EM:
                 self.logL.append(float(acc["scal"][1]))
             if callback is not None:
                 callback(it, W, theta)
-        th = theta.cpu().numpy()
-        self.lparams = {"W": W, "pi": float(th[0]), "sigma": float(th[1])}
+        self.lparams = m._params_from_theta(W, theta.cpu().numpy())
         return self.lparams

@@ -26,3 +26,15 @@ def test_linear_annealing_rejects(kw):
 def test_model_rejects_truncation(Hp, gamma):
     with pytest.raises(ValueError):
         BSC_ET(25, 10 if Hp != 33 else 40, Hp, gamma, device=0)
+
+
+def test_dsc_model_checks_its_value_set():
+    from paper_1908_06843_amd import em
+    m = em.DSC_ET(16, 8, 4, 2, (0.0, 1.0, -1.0), device=0)
+    assert m.kind == "dsc" and m._nvalues() == 3
+    assert m._theta({"pv": (0.8, 0.1, 0.1), "sigma": 0.5}) == pytest.approx(
+        [0.2, 0.5, 0.8, 0.1, 0.1])
+    with pytest.raises(ValueError):
+        em.DSC_ET(16, 8, 4, 2, (1.0, 2.0), device=0)
+    with pytest.raises(ValueError):
+        em.DSC_ET(16, 8, 4, 2, (0.0,), device=0)

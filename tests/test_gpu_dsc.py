@@ -13,7 +13,7 @@ import pytest
 
 import synth
 from oracle import prosper_oracle as O
-from tests._common import assert_parity
+from tests._common import assert_parity, parity_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -240,3 +240,76 @@ def test_dsc_edge_cases():
     with pytest.raises(api.ProsperError):
         api.estep(torch.tensor(Y, device=dev), torch.tensor(W, device=dev), sigma=1.0,
                   Hprime=3, gamma=2, model="dsc", phi=(0.0, 1.0, 1.0), pv=(0.8, 0.1, 0.1))
+
+
+def test_dsc_full_workload_sampled():
+    """The full DSC workload (N = 100000) in the benchmark's form (BF16
+    projection, statistics accumulated, walk over the whole grid-stride
+    range): 256 sampled points against the oracle one by one, and the sums
+    against what holds at any size (value counts add up to sum <k>, which
+    lies within [0, gamma N]; B's diagonal is sum <s_h^2>)."""
+    import torch
+    from paper_1908_06843_amd import api
+    Y, W, phi, pv, sigma = dsc_problem(WL.N, "init")
+    dev = torch.device("cuda", 0)
+    acc = api.new_acc("dsc", WL.D, WL.H, nvalues=len(phi))
+    out = api.estep(torch.tensor(Y, device=dev), torch.tensor(W, device=dev), sigma=sigma,
+                    Hprime=WL.Hprime, gamma=WL.gamma, model="dsc", precision="bf16", phi=phi,
+                    pv=pv, acc=acc, factor_b=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    idx = np.sort(synth.rng(3).choice(WL.N, 256, replace=False))
+    r = O.dsc_estep(Y[idx], W, phi, pv, sigma, WL.Hprime, WL.gamma)
+    assert_parity(g, r, "bf16", "dsc full workload (sample)", idx=idx)
+    vc = acc["vcount"].cpu().numpy()
+    sc = acc["scal"].cpu().numpy()
+    assert sc[4] == WL.N
+    assert vc[1:].sum() == pytest.approx(sc[0], rel=1e-6)
+    assert 0.0 <= sc[0] <= WL.gamma * WL.N
+    B = acc["B"].cpu().numpy()
+    assert np.all(np.diag(B) >= 0.0)
+    assert float(np.diag(B).sum()) <= (max(abs(p) for p in phi) ** 2) * sc[0] * (1 + 1e-5)
+
+
+def test_dsc_compiled_walk_hands_off_overflowing_points():
+    """(H', gamma) = (8, 3) runs the compiled walk; its pivot is the best
+    state with at most two actives, so points whose best state has three
+    actives far above it (here: three components at phi = +-2, little
+    noise) would overflow its weights and go to the table-driven kernel.
+    Every point, handed off or not, matches the oracle, and so do the sums."""
+    phi, pv = WL.phi, WL.pv
+    N, D, H = 150, 64, 30
+    gen = synth.rng(81)
+    W = synth.unit_norm_gaussian_dictionary(gen, D, H)
+    S = np.zeros((N, H))
+    for n in range(N):
+        if n % 3:   # two in three points: three strong actives
+            S[n, gen.choice(H, 3, replace=False)] = gen.choice([2.0, -2.0], 3)
+        else:
+            S[n, gen.choice(H, 1)] = 1.0
+    Y = (S @ W.T + 0.05 * gen.standard_normal((N, D))).astype(np.float32)
+    W = W.astype(np.float32)
+    # the oracle's log-joints show that points do cross the hand-off line:
+    # best state above the best with <= 2 actives by more than 64 log2 units
+    crossing = 0
+    for n in range(0, N, 10):
+        pt = O.dsc_estep_point(Y[n], W, phi, pv, 0.05, 8, 3)
+        k = np.array([len(sl) for sl, _ in O.dsc_state_table(len(phi), 8, 3)])
+        gap = (pt["lj"].max() - pt["lj"][k <= 2].max()) / np.log(2.0)
+        crossing += int(gap > 64.0)
+    assert crossing >= 5
+    g = run_gpu(Y, W, phi, pv, 0.05, 8, 3, accumulate=True)
+    r = O.dsc_estep(Y, W, phi, pv, 0.05, 8, 3)
+    st = parity_stats(g, r)
+    print(f"[parity] dsc hand-off: {st}", flush=True)
+    assert st["sel_mismatch"] == 0 and st["s_max"] <= 1e-5
+    # logL is a small difference of terms of size lam ||y||^2 (~2400 here):
+    # FP32 rounding is relative to those terms, not to logL
+    scale = np.maximum(np.abs(r["logL"]), (Y.astype(np.float64) ** 2).sum(1) / (2 * 0.05 ** 2))
+    assert np.all(np.abs(g["logL"] - r["logL"]) <= 1e-5 * scale)
+    if np.asarray(r["flagged"], dtype=bool).any():
+        r = O.dsc_estep(Y, W, phi, pv, 0.05, 8, 3, sel=g["sel"])
+    Bg = np.triu(g["B"]) + np.triu(g["B"], 1).T
+    assert rel(g["A"], r["A"]) < 2e-5 and rel(Bg, r["B"]) < 2e-5
+    assert rel(g["vcount"][1:], r["vcount"][1:]) < 1e-5
+    assert g["scal"][1] == pytest.approx(r["scal"][1], rel=1e-5)

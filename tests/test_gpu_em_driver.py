@@ -82,3 +82,63 @@ def test_inference_top_states(name, N, Hp, gamma, cls):
             assert abs(p[n, t] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
         checked += 1
     assert checked > 0.9 * N
+
+
+def test_dsc_annealed_em_and_inference():
+    """DSC_ET through EM.run: each annealed iteration against the oracle's
+    DSC step (tempered E-step, W = A B^-1, sigma by the direct sweep, pv from
+    the value counts), then inference's top states against the oracle's."""
+    import torch
+    from paper_1908_06843_amd import em
+    wl = synth.WORKLOADS["dsc"]
+    N, Hp, gamma = 240, wl.Hprime, wl.gamma
+    Y, Wgt, _, _ = synth.make_workload("dsc", N=N)
+    model = em.DSC_ET(wl.D, wl.H, Hp, gamma, wl.phi, precision="fp32", device=0)
+    params = model.standard_init({"y": Y}, seed=5)
+    anneal = em.LinearAnnealing(2, beta_start=0.7)
+    hist = [(params["W"].cpu().numpy().astype(np.float64), params["pv"], params["sigma"])]
+
+    def keep(it, W, theta):
+        th = theta.cpu().numpy()
+        hist.append((W.cpu().numpy().astype(np.float64), tuple(th[2:]), float(th[1])))
+
+    run = em.EM(model, anneal, data={"y": Y}, lparams=params)
+    out = run.run(callback=keep)
+    for it in range(2):
+        W, pv, sigma = hist[it]
+        r = O.dsc_estep(Y, W, wl.phi, pv, sigma, Hp, gamma, keep_posterior=True,
+                        beta=anneal.beta(it))
+        Wr, pvr, sr = O.dsc_mstep(Y, W, r)
+        Wg, pvg, sg = hist[it + 1]
+        print(f"[em] dsc it={it}: W {rel(Wg, Wr):.2e} sigma {sg} vs {sr}", flush=True)
+        assert rel(Wg, Wr) < 1e-4
+        np.testing.assert_allclose(pvg, pvr, rtol=1e-5)
+        assert sg == pytest.approx(sr, rel=1e-5)
+        assert run.logL[it] == pytest.approx(r["scal"][1], rel=1e-5)
+    assert out["pv"] == pytest.approx(hist[-1][1])
+    # inference at the generating parameters: the returned states carry the
+    # oracle's probabilities of their ranks
+    gt = {"W": Wgt, "sigma": wl.sigma, "pv": wl.pv}
+    res = model.inference(anneal, gt, Y, topk=3, beta=1.0)
+    s, p = res["s"].cpu().numpy(), res["p"].cpu().numpy()
+    assert s.shape == (N, 3, wl.H)
+    r = O.dsc_estep(Y, Wgt, wl.phi, wl.pv, wl.sigma, Hp, gamma, topk=3)
+    pos = {v: c for c, v in enumerate(wl.phi)}
+    checked = 0
+    for n in range(N):
+        if r["flagged"][n] or not np.array_equal(res["sel"][n].cpu().numpy(), r["sel"][n]):
+            continue
+        pt = O.dsc_estep_point(Y[n], Wgt, wl.phi, wl.pv, wl.sigma, Hp, gamma)
+        sel = r["sel"][n]
+        for t in range(3):
+            vec = s[n, t]
+            assert np.all(vec[np.setdiff1d(np.arange(wl.H), sel)] == 0)
+            sub = vec[sel]
+            key = (tuple(j for j in range(Hp) if sub[j] != 0),
+                   tuple(pos[float(sub[j])] for j in range(Hp) if sub[j] != 0))
+            i = r["table"].index(key)
+            q_ref = r["top_q"][n, t]
+            assert abs(pt["q"][i] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
+            assert abs(p[n, t] - q_ref) <= 3e-5 * max(q_ref, 1e-3) + 1e-7
+        checked += 1
+    assert checked > 0.8 * N
