@@ -63,13 +63,19 @@ typedef enum {
 } prosper_model;
 
 /* Precision of the N x D x H projection contraction (W^T y for all latents).
- *  PROSPER_FP32: FP32 MFMA (v_mfma_f32_16x16x4_f32), FP32 accumulation.
- *  PROSPER_BF16: BF16 MFMA with FP32 accumulation; each operand is split into
- *                a BF16 head and a BF16 tail and three products are summed
- *                (head*head + head*tail + tail*head).
+ *  PROSPER_FP32:   FP32 MFMA (v_mfma_f32_16x16x4_f32), FP32 accumulation.
+ *  PROSPER_BF16:   BF16 MFMA with FP32 accumulation; each operand is split into
+ *                  a BF16 head and a BF16 tail and three products are summed
+ *                  (head*head + head*tail + tail*head).
+ *  PROSPER_BF16X1: one BF16 product (the heads) with FP32 accumulation for the
+ *                  ranking, then b of the H' selected candidates recomputed in
+ *                  FP32 from y and W (the FP32 fix-up the state walk uses).  The
+ *                  wider error band of the single product sends more points
+ *                  through the exact re-scoring; the selection stays exact.
+ *                  E-step only (EINVAL in prosper_serve).
  * Everything after the projection (state log-joints, normalisation, moments)
  * runs in FP32; M-step solve and the sigma/pi reductions run in FP64. */
-typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1 } prosper_precision;
+typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1, PROSPER_BF16X1 = 2 } prosper_precision;
 
 /* Flags for prosper_args.flags */
 #define PROSPER_FLAG_NONE          0u

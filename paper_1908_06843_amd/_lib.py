@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libprosper.so")
 
 MODELS = {"bsc": 0, "tsc": 1, "mca": 2, "mmca": 3, "dsc": 4}
-PRECISIONS = {"fp32": 0, "bf16": 1}
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x1": 2}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY",
           -5: "ENOTFOUND", -6: "ETIMEDOUT"}
 

@@ -261,7 +261,8 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
       }
     }
   }
-  if (a->precision != PROSPER_FP32 && a->precision != PROSPER_BF16) {
+  if (a->precision != PROSPER_FP32 && a->precision != PROSPER_BF16 &&
+      a->precision != PROSPER_BF16X1) {
     *msg = "unknown precision";
     return PROSPER_EINVAL;
   }
@@ -370,8 +371,8 @@ size_t prep_bytes(int Dp, int H, int prec) {
   size_t b = 0;
   auto add = [&](size_t n) { b = ((b + 255) & ~(size_t)255) + n; };
   add((size_t)H * Dp * 4);
-  add(prec == PROSPER_BF16 ? (size_t)H * Dp * 2 : 0);
-  add(prec == PROSPER_BF16 ? (size_t)H * Dp * 2 : 0);
+  add(prec != PROSPER_FP32 ? (size_t)H * Dp * 2 : 0);
+  add(prec != PROSPER_FP32 ? (size_t)H * Dp * 2 : 0);
   add((size_t)H * H * 4);
   add((size_t)H * 4);
   add((size_t)H * 4);
@@ -385,8 +386,8 @@ Prepared carve_prep(void* base, int Dp, int H, int prec) {
   Carve cv{reinterpret_cast<char*>(base)};
   Prepared p;
   p.Pt32 = cv.take<float>((size_t)H * Dp);
-  p.Pt_hi = cv.take<bf16>(prec == PROSPER_BF16 ? (size_t)H * Dp : 0);
-  p.Pt_lo = cv.take<bf16>(prec == PROSPER_BF16 ? (size_t)H * Dp : 0);
+  p.Pt_hi = cv.take<bf16>(prec != PROSPER_FP32 ? (size_t)H * Dp : 0);
+  p.Pt_lo = cv.take<bf16>(prec != PROSPER_FP32 ? (size_t)H * Dp : 0);
   p.G = cv.take<float>((size_t)H * H);
   p.hn_hi = cv.take<float>(H);
   p.hn_lo = cv.take<float>(H);
@@ -775,7 +776,7 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
   Prepared p = carve_prep(c->prep.p, Dp, H, prec);
 
   const EstepLayout L =
-      plan_estep(a, out, c->num_cu, project_defer_capacity(a->N, H, Hp));
+      plan_estep(a, out, c->num_cu, project_defer_capacity(a->N, H, Hp, prec));
   e = ensure(c->scratch, L.bytes + 256);
   if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "workspace (per point) allocation failed");
   Scratch sc = carve_estep(c->scratch.p, L, a, out);

@@ -159,8 +159,8 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
   const int relu = (model == PROSPER_MCA && H > 1) ? 1 : 0;
   dim3 gt((Dp + 31) / 32, (H + 31) / 32);
   hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, st, W, D, H, Dp, relu, p.Pt32,
-                     prec == PROSPER_BF16 ? p.Pt_hi : nullptr,
-                     prec == PROSPER_BF16 ? p.Pt_lo : nullptr);
+                     prec != PROSPER_FP32 ? p.Pt_hi : nullptr,
+                     prec != PROSPER_FP32 ? p.Pt_lo : nullptr);
   if (!is_max_model(model)) {
     dim3 gg((H + 15) / 16, (H + 15) / 16);
     hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G);

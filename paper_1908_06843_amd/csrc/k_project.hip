@@ -167,12 +167,14 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
             hi[1] = (bf16)x.y;
             hi[2] = (bf16)x.z;
             hi[3] = (bf16)x.w;
-            lo[0] = (bf16)(x.x - (float)hi[0]);
-            lo[1] = (bf16)(x.y - (float)hi[1]);
-            lo[2] = (bf16)(x.z - (float)hi[2]);
-            lo[3] = (bf16)(x.w - (float)hi[3]);
             *reinterpret_cast<bf16x4*>(&Yh[r * (Dp + 8) + 4 * c4]) = hi;
-            *reinterpret_cast<bf16x4*>(&Yl[r * (Dp + 8) + 4 * c4]) = lo;
+            if constexpr (PREC == PROSPER_BF16) {
+              lo[0] = (bf16)(x.x - (float)hi[0]);
+              lo[1] = (bf16)(x.y - (float)hi[1]);
+              lo[2] = (bf16)(x.z - (float)hi[2]);
+              lo[3] = (bf16)(x.w - (float)hi[3]);
+              *reinterpret_cast<bf16x4*>(&Yl[r * (Dp + 8) + 4 * c4]) = lo;
+            }
           }
           double a = part[rr];
           a = fma((double)x.x, (double)x.x, a);
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
   // ---- 2. b = P y for the tile: MFMA, FP32 accumulation
   // BF16: head*head products in acc, the two cross products in accx (kept
   // apart so that the accumulation error of each is relative to its own
-  // magnitude); FP32 uses acc only
+  // magnitude); FP32 and the single BF16 product (BF16X1) use acc only
   constexpr int NX = (PREC == PROSPER_BF16) ? 4 : 1;
   f32x4 acc[4][4], accx[NX][4];
 #pragma unroll
@@ -270,6 +272,8 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
       }
     } else {
       // 16x16x32 BF16: MFMA j (0, 1) of a block takes depths 16 q + 8 j .. + 8
+      // (BF16X1: the head*head product only)
+      constexpr bool SPLIT = PREC == PROSPER_BF16;
       const bf16* Yh = reinterpret_cast<const bf16*>(smem);
       const int ys = Dp + 8;
       const bf16* Yl = Yh + TM * ys;
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           bh[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_hi[boff[nt] + 8 * j]);
-          bl[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_lo[boff[nt] + 8 * j]);
+          if constexpr (SPLIT) bl[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_lo[boff[nt] + 8 * j]);
         }
       for (int t = 0; t < Dp; t += 64) {
         const int tn = (t + 64 < Dp) ? t + 64 : t;
@@ -289,7 +293,8 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             bhn[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_hi[boff[nt] + tn + 8 * j]);
-            bln[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_lo[boff[nt] + tn + 8 * j]);
+            if constexpr (SPLIT)
+              bln[nt][j] = *reinterpret_cast<const i32x4*>(&Pt_lo[boff[nt] + tn + 8 * j]);
           }
         const i32x4 zero = {0, 0, 0, 0};
 #pragma unroll
@@ -299,19 +304,21 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
           for (int mt = 0; mt < MT; ++mt) {
             const int o = (mt * 16 + r16) * ys + t + 16 * q + 8 * j;
             ah[mt] = *reinterpret_cast<const bf16x8*>(&Yh[o]);
-            al[mt] = *reinterpret_cast<const bf16x8*>(&Yl[o]);
+            if constexpr (SPLIT) al[mt] = *reinterpret_cast<const bf16x8*>(&Yl[o]);
           }
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt) {
             const bf16x8 bhv = __builtin_bit_cast(bf16x8, bval[nt] ? bh[nt][j] : zero);
-            const bf16x8 blv = __builtin_bit_cast(bf16x8, bval[nt] ? bl[nt][j] : zero);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
               f32x4& c = acc[gi * MT + mt][nt];
-              f32x4& cx = accx[(gi * MT + mt) % NX][nt];
               c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bhv, c, 0, 0, 0);
-              cx = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], blv, cx, 0, 0, 0);
-              cx = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bhv, cx, 0, 0, 0);
+              if constexpr (SPLIT) {
+                const bf16x8 blv = __builtin_bit_cast(bf16x8, bval[nt] ? bl[nt][j] : zero);
+                f32x4& cx = accx[(gi * MT + mt) % NX][nt];
+                cx = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], blv, cx, 0, 0, 0);
+                cx = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bhv, cx, 0, 0, 0);
+              }
             }
           }
         }
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(256, 2) void k_project_select(
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             bh[nt][j] = bhn[nt][j];
-            bl[nt][j] = bln[nt][j];
+            if constexpr (SPLIT) bl[nt][j] = bln[nt][j];
           }
       }
     }
@@ -514,6 +521,39 @@ __global__ __launch_bounds__(256) void k_select_deferred(
   }
 }
 
+// The FP32 fix-up of the single-product form (BF16X1): b of every selected
+// candidate recomputed from y and the FP32 projection row, so that the state
+// walk starts from FP32-accurate b.  One wave per point; each lane holds up
+// to 16 depths of y in registers and sums its products with one rounding per
+// fused multiply-add before a butterfly sum over the wave.
+__global__ __launch_bounds__(256) void k_fixup_bc(const float* __restrict__ Y, int64_t N, int D,
+                                                  int Dp, const float* __restrict__ Pt32,
+                                                  const int32_t* __restrict__ sel,
+                                                  float* __restrict__ bc, int Hp) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nd = (D + 63) >> 6;  // <= 16 (D <= 1024)
+  for (int64_t n = (int64_t)blockIdx.x * 4 + wave; n < N; n += (int64_t)gridDim.x * 4) {
+    float y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int d = 64 * k + lane;
+      y[k] = (k < nd && d < D) ? Y[n * D + d] : 0.0f;
+    }
+    for (int j = 0; j < Hp; ++j) {
+      const int64_t row = (int64_t)sel[n * Hp + j] * Dp;
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int d = 64 * k + lane;
+        if (k < nd && d < D) a = __builtin_fmaf(y[k], Pt32[row + d], a);
+      }
+      a = wave_sum(a);
+      if (lane == 0) bc[n * Hp + j] = a;
+    }
+  }
+}
+
 template <int PREC, int TM, int RM, bool FAST, bool DSC = false>
 static hipError_t launch_ps(const float* Y, int64_t N, int D, int Dp, int H, int Hp,
                             int score_abs, float kappa, const Prepared& p, const Scratch& s,
@@ -561,15 +601,34 @@ static int choose_tm(int Dp, int H, int prec) {
   return tm;
 }
 
-int project_defer_capacity(int64_t N, int H, int Hp) {
+int project_defer_capacity(int64_t N, int H, int Hp, int prec) {
   if (!(Hp <= FAST_HP && Hp < H) || N <= 0) return 0;
-  return (int)std::min<int64_t>(std::min<int64_t>(N, N / 4 + 1024), 1 << 24);
+  // the single-product form's wide band sends most points to the exact path
+  const int64_t want = prec == PROSPER_BF16X1 ? N : N / 4 + 1024;
+  return (int)std::min<int64_t>(std::min<int64_t>(N, want), 1 << 24);
 }
+
+static hipError_t launch_project_select_body(int model, int prec, const float* Y, int64_t N,
+                                             int D, int Dp, int H, int Hp, const Prepared& p,
+                                             const Scratch& s, uint8_t* flagged, double* scal,
+                                             hipStream_t st);
 
 hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N, int D, int Dp,
                                  int H, int Hp, const Prepared& p, const Scratch& s,
                                  uint8_t* flagged, double* scal, hipStream_t st) {
   if (N <= 0) return hipSuccess;
+  hipError_t e = launch_project_select_body(model, prec, Y, N, D, Dp, H, Hp, p, s, flagged, scal, st);
+  if (e != hipSuccess || prec != PROSPER_BF16X1) return e;
+  const int64_t nwg = std::min<int64_t>((N + 3) / 4, 2048);
+  hipLaunchKernelGGL(k_fixup_bc, dim3((unsigned)nwg), dim3(256), 0, st, Y, N, D, Dp, p.Pt32, s.sel,
+                     s.bc, Hp);
+  return hipGetLastError();
+}
+
+static hipError_t launch_project_select_body(int model, int prec, const float* Y, int64_t N,
+                                             int D, int Dp, int H, int Hp, const Prepared& p,
+                                             const Scratch& s, uint8_t* flagged, double* scal,
+                                             hipStream_t st) {
   const int score_abs =
       (model == PROSPER_TSC) ? SCORE_ABS : (model == PROSPER_DSC ? SCORE_DSC : SCORE_LIN);
   // Bound on |computed b - exact b| per unit of ||y|| ||P_h|| (Cauchy-Schwarz
@@ -580,11 +639,16 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
   // exact in FP32; the head*head sum sees D + 1 roundings, the cross sum
   // (terms below 2^-7 of the head*head ones) 2 D + 1, and one rounding adds
   // the two.  3% slack.
+  // BF16X1 (one head*head product): each operand's head is within 2^-9 of
+  // it, so a product is within 2^-8 + 2^-18 of y_d P_hd (exact in FP32), plus
+  // the D + 1 roundings of the accumulation.
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float kappa =
       (prec == PROSPER_FP32)
           ? (float)(1.01 * (D + 2) * u)
-          : (float)(1.03 * (3.0 / 65536.0 + (D + 2) * u + (2.0 * D + 1) * u / 128.0 + u));
+          : (prec == PROSPER_BF16X1)
+                ? (float)(1.03 * (1.0 / 256.0 + 1.0 / 262144.0 + (D + 2) * u))
+                : (float)(1.03 * (3.0 / 65536.0 + (D + 2) * u + (2.0 * D + 1) * u / 128.0 + u));
   const int tm = choose_tm(Dp, H, prec);
   const size_t lds = project_lds_bytes(Dp, H, prec, tm);
   const int Hpad = round_up(H, 64);
@@ -601,9 +665,11 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
       if (tm == 32) PS_DSC(PROSPER_FP32, 32);
       PS_DSC(PROSPER_FP32, 16);
     }
-    if (tm == 64) PS_DSC(PROSPER_BF16, 64);
-    if (tm == 32) PS_DSC(PROSPER_BF16, 32);
-    PS_DSC(PROSPER_BF16, 16);
+    if (prec == PROSPER_BF16) {
+      if (tm == 64) PS_DSC(PROSPER_BF16, 64);
+      if (tm == 32) PS_DSC(PROSPER_BF16, 32);
+      PS_DSC(PROSPER_BF16, 16);
+    }
 #undef PS_DSC
   }
 #define PS_CASE(P, T, R)                                                                       \
@@ -620,7 +686,7 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
     }
     if (tm == 32) PS_CASE(PROSPER_FP32, 32, 16);
     PS_CASE(PROSPER_FP32, 16, 16);
-  } else {
+  } else if (prec == PROSPER_BF16) {
     if (small) {
       if (tm == 64) PS_CASE(PROSPER_BF16, 64, 4);
       if (tm == 32) PS_CASE(PROSPER_BF16, 32, 4);
@@ -628,6 +694,14 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
     }
     if (tm == 32) PS_CASE(PROSPER_BF16, 32, 16);
     PS_CASE(PROSPER_BF16, 16, 16);
+  } else {
+    if (small) {
+      if (tm == 64) PS_CASE(PROSPER_BF16X1, 64, 4);
+      if (tm == 32) PS_CASE(PROSPER_BF16X1, 32, 4);
+      PS_CASE(PROSPER_BF16X1, 16, 4);
+    }
+    if (tm == 32) PS_CASE(PROSPER_BF16X1, 32, 16);
+    PS_CASE(PROSPER_BF16X1, 16, 16);
   }
 #undef PS_CASE
 }

@@ -146,7 +146,7 @@ prosper_status prosper_estep_static(const prosper_args* a, const float* Y, const
   const size_t per_entry = (size_t)(L.Hpad + 8) * 4;
   const int64_t room =
       ((int64_t)cap - (int64_t)fixed - (int64_t)L.bytes - 512) / (int64_t)per_entry;
-  int64_t dcap = project_defer_capacity(a->N, H, Hp);
+  int64_t dcap = project_defer_capacity(a->N, H, Hp, a->precision);
   if (dcap > room) dcap = room > 0 ? room : 0;
   L = plan_estep(a, out, ncu_s, (int)dcap);
   if (fixed + L.bytes + 256 > cap) L = plan_estep(a, out, ncu_s, 0);

@@ -156,7 +156,7 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
                        const Prepared& p, hipStream_t st);
 // Entries of the projection's deferral list for N points: enough for a
 // quarter of them (0 where every point takes the exact path anyway).
-int project_defer_capacity(int64_t N, int H, int Hp);
+int project_defer_capacity(int64_t N, int H, int Hp, int prec = PROSPER_BF16);
 hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N, int D, int Dp,
                                  int H, int Hp, const Prepared& p, const Scratch& s,
                                  uint8_t* flagged, double* scal, hipStream_t st);

@@ -25,7 +25,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x1"])
 @pytest.mark.parametrize("theta", ["gt", "init"])
 @pytest.mark.parametrize("name,N,Hp,gamma", CASES)
 def test_estep_parity(name, N, Hp, gamma, theta, prec):
@@ -125,7 +125,7 @@ def test_topk_matches_oracle(model, name, N, Hp, gamma):
     assert checked > 0.9 * N
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x1"])
 def test_full_size_bsc256_sampled(prec):
     """The benchmark configuration (N = 200000) on the GPU, checked against the
     oracle on a seeded sample of points (every output is per point), plus
