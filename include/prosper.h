@@ -36,7 +36,10 @@
  *  - Matrices are row-major, float32 unless stated:
  *      Y  N x D   data, row n is y_n
  *      W  D x H   dictionary, column h is component W_h  (f = W s)
- *  - A context is not thread-safe; use one per host thread.
+ *  - A context is not thread-safe; use one per host thread.  Its calls share
+ *    one device workspace: calls on different streams of one context must not
+ *    overlap on the device (order them, e.g. with an event, or use one context
+ *    per stream).
  */
 #ifndef PROSPER_H
 #define PROSPER_H
