@@ -76,7 +76,7 @@ __all__ = [
     "BSC", "TSC", "MCA", "MMCA", "MODELS", "MAX_MODELS", "TIE_REL",
     "state_table", "state_masks", "log_prior", "superposition", "log_joint",
     "selection_scores", "preselect", "estep_point", "estep", "mstep",
-    "em_run", "free_energy", "DSC", "dsc_state_table", "dsc_state_count",
+    "em_run", "free_energy", "truncated_prior_moments", "mstep_et", "DSC", "dsc_state_table", "dsc_state_count",
     "dsc_log_joint", "dsc_selection_scores", "dsc_estep_point", "dsc_estep", "dsc_mstep",
 ]
 
@@ -368,6 +368,57 @@ def mstep(model: str, Y: np.ndarray, W_old: np.ndarray, est: Dict,
             tot += float(q @ (R * R).sum(axis=1))
         sigma2 = tot / (N * D)
     return W_new, float(pi_new), float(np.sqrt(sigma2))
+
+
+# --------------------------------------------------------------------------
+# M-step variant: pi and sigma from the points best explained by <= gamma
+# causes (deterministic-annealing section's "M-step variants"; a reading,
+# the paper gives no formula)
+# --------------------------------------------------------------------------
+def truncated_prior_moments(H: int, gamma: int, pi: float) -> Tuple[float, float]:
+    """A = P(#non-zero latents <= gamma) and B = E[#non-zero; #non-zero <= gamma]
+    under the prior of Eq. 1 with H independent latents, each non-zero with
+    probability pi (BSC, and TSC's two signs together)."""
+    A = B = 0.0
+    for k in range(0, min(gamma, H) + 1):
+        p = math.comb(H, k) * pi ** k * (1.0 - pi) ** (H - k)
+        A += p
+        B += k * p
+    return A, B
+
+
+def mstep_et(model: str, Y: np.ndarray, W_old: np.ndarray, est: Dict, pi: float,
+             gamma: int):
+    """BSC/TSC M-step with pi and sigma taken from the selected points:
+    W_new as `mstep` (all points); M = the N_cut = clamp(round(N A(pi)), 1, N)
+    points with the largest logL_n (ties to the lower index) -- the share of
+    prior draws with at most gamma causes;
+      pi_new = pi * mean_{n in M} <k>_n * A(pi) / B(pi)   (pi if B = 0),
+    which maps the mean number of causes among truncated explanations
+    (B/A at the generating pi) back to pi; and
+      sigma_new^2 = sum_{n in M} sum_s q_n(s) ||y_n - W_old s||^2 / (N_cut D)
+    with the W of the E-step.  Needs keep_posterior.  Returns
+    (W_new, pi_new, sigma_new, M)."""
+    if model not in (BSC, TSC):
+        raise ValueError("the selected-points M-step is defined for BSC and TSC")
+    Y = np.asarray(Y, dtype=np.float64)
+    W_old = np.asarray(W_old, dtype=np.float64)
+    N, D = Y.shape
+    H = W_old.shape[1]
+    W_new, _, _ = mstep(model, Y, W_old, est)
+    A, B = truncated_prior_moments(H, gamma, pi)
+    n_cut = min(N, max(1, int(round(N * A))))
+    logL = est["logL"]
+    M = sorted(range(N), key=lambda n: (-logL[n], n))[:n_cut]
+    kbar = float(np.mean(est["k_mean"][M]))
+    pi_new = pi * kbar * A / B if B > 0.0 else pi
+    tot = 0.0
+    for n in M:
+        c, q = est["posterior"][n]
+        S = _embed(est["table"], c, H)
+        R = Y[n][None, :] - S @ W_old.T
+        tot += float(q @ (R * R).sum(axis=1))
+    return W_new, float(pi_new), float(np.sqrt(tot / (n_cut * D))), np.array(sorted(M))
 
 
 def em_run(model: str, Y: np.ndarray, W0: np.ndarray, pi0: float, sigma0: float,
