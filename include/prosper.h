@@ -151,6 +151,10 @@ typedef struct {
                            descending; equal q ordered by canonical state order */
     uint8_t*  flagged;  /* N        1 if the H'-th and (H'+1)-th selection scores
                                     are within 1e-6 relative (max(1,|r|)) */
+    /* BSC/TSC only (EINVAL for the other models); either one present runs the
+     * table-driven state walk.  They feed prosper_mstep_et. */
+    float*    k_mean;   /* N        <number of non-zero latents> under q_n */
+    float*    res;      /* N        <||y_n - W s||^2> under q_n, with the W of this call */
 } prosper_point_out;
 
 /* Sufficient statistics for the M-step, accumulated (added) by prosper_estep
@@ -283,6 +287,24 @@ prosper_status prosper_estep_static(const prosper_args* args, const float* Y, co
 prosper_status prosper_mstep(prosper_ctx* ctx, const prosper_args* args,
                              const prosper_acc* acc, const float* W_old, float* W_new,
                              double* theta_new, void* stream);
+
+/* M-step variant with pi and sigma from the selected points ---------------
+ * The deterministic-annealing section names M-step variants without a
+ * formula; this is the reading taken (BSC/TSC).  W_new as prosper_mstep,
+ * from all points.  The points kept are the N_cut = clamp(round(N A), 1, N)
+ * with the largest logL_n (ties to the lower index), A = P(#non-zero <= gamma)
+ * under the prior with the E-step's pi; with B = E[#non-zero; #non-zero <=
+ * gamma] under the same prior:
+ *   pi_new    = pi * mean_kept <k>_n * A / B      (pi when B = 0)
+ *   sigma_new = sqrt(sum_kept res_n / (N_cut D))  (res of the E-step's W)
+ * logL, k_mean, res: device, N each, as written by prosper_estep (N = args->N).
+ * The E-step's pi is args->theta_dev[0] when set, else args->pi; args supplies
+ * model, N, D, H, gamma.  theta_new (device, 2 doubles) may equal theta_dev.
+ * Errors as prosper_mstep, plus EINVAL for another model or N < 1. */
+prosper_status prosper_mstep_et(prosper_ctx* ctx, const prosper_args* args,
+                                const prosper_acc* acc, const float* logL,
+                                const float* k_mean, const float* res, const float* W_old,
+                                float* W_new, double* theta_new, void* stream);
 
 /* Serving: E-step-only posterior inference with continuous batching ------
  * The `inference` method of the user-interface section: for each data point

@@ -44,7 +44,8 @@ class Args(C.Structure):
 
 class PointOut(C.Structure):
     _fields_ = [("sel", C.c_void_p), ("s_mean", C.c_void_p), ("logL", C.c_void_p),
-                ("top_mask", C.c_void_p), ("top_q", C.c_void_p), ("flagged", C.c_void_p)]
+                ("top_mask", C.c_void_p), ("top_q", C.c_void_p), ("flagged", C.c_void_p),
+                ("k_mean", C.c_void_p), ("res", C.c_void_p)]
 
 
 class Acc(C.Structure):
@@ -55,7 +56,7 @@ class Acc(C.Structure):
 EXPORTS = [
     "prosper_ctx_create", "prosper_ctx_destroy", "prosper_last_error",
     "prosper_validate_args", "prosper_state_count", "prosper_state_table",
-    "prosper_estep", "prosper_mstep", "prosper_serve", "prosper_serve_submit",
+    "prosper_estep", "prosper_mstep", "prosper_mstep_et", "prosper_serve", "prosper_serve_submit",
     "prosper_serve_wait", "prosper_serve_wait_stages", "prosper_serve_stop",
     "prosper_profile", "prosper_profile_read",
     "prosper_estep_static", "prosper_dsc_state_count", "prosper_dsc_state_table",
@@ -98,6 +99,9 @@ def load() -> C.CDLL:
     lib.prosper_estep_static.restype = i32
     lib.prosper_mstep.argtypes = [vp, C.POINTER(Args), C.POINTER(Acc), vp, vp, vp, vp]
     lib.prosper_mstep.restype = i32
+    lib.prosper_mstep_et.argtypes = [vp, C.POINTER(Args), C.POINTER(Acc), vp, vp, vp, vp, vp, vp,
+                                     vp]
+    lib.prosper_mstep_et.restype = i32
     lib.prosper_serve.argtypes = [vp, vp, i32, i32, i32, i32, dbl, dbl, i32, sz, i32, i32, i32,
                                   C.POINTER(vp)]
     lib.prosper_serve.restype = i32

@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["Context", "context", "estep", "mstep", "new_acc", "zero_acc", "state_count",
+__all__ = ["Context", "context", "estep", "mstep", "mstep_et", "new_acc", "zero_acc", "state_count",
            "state_table", "dsc_state_count", "dsc_state_table", "ProsperError"]
 
 ProsperError = _lib.ProsperError
@@ -117,7 +117,9 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
 
     Returns the requested per-point outputs: sel (N x H' int32), s_mean
-    (N x H'), logL (N), flagged (N uint8), top_mask / top_q (N x topk).
+    (N x H'), logL (N), flagged (N uint8), top_mask / top_q (N x topk), and
+    for BSC/TSC k_mean and res (N each: <#non-zero> and <||y - W s||^2>, the
+    inputs of `mstep_et`).
     `theta` (2 doubles on the device: pi, sigma) overrides pi and sigma.
     `out` may supply preallocated output tensors (same keys).
     `factor_b` (with `acc`, BSC/TSC): this call completes the accumulation;
@@ -159,12 +161,16 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
         res["logL"] = get("logL", (N,), torch.float32)
     if "flagged" in want or "flagged" in out:
         res["flagged"] = get("flagged", (N,), torch.uint8)
+    for key in ("k_mean", "res"):   # BSC/TSC: per-point inputs of mstep_et
+        if key in want or key in out:
+            res[key] = get(key, (N,), torch.float32)
     if topk:
         mshape = {"tsc": (N, topk, 2), "dsc": (N, topk, 4)}.get(model, (N, topk))
         res["top_mask"] = get("top_mask", mshape, torch.int32)
         res["top_q"] = get("top_q", (N, topk), torch.float32)
     po = _lib.PointOut(_ptr(res.get("sel")), _ptr(res.get("s_mean")), _ptr(res.get("logL")),
-                       _ptr(res.get("top_mask")), _ptr(res.get("top_q")), _ptr(res.get("flagged")))
+                       _ptr(res.get("top_mask")), _ptr(res.get("top_q")), _ptr(res.get("flagged")),
+                       _ptr(res.get("k_mean")), _ptr(res.get("res")))
     accs = None
     if acc is not None:
         accs = _acc_struct(acc)
@@ -209,4 +215,31 @@ def mstep(acc: Dict[str, torch.Tensor], W_old: torch.Tensor, *, model: str = "bs
     _lib.check(_lib.load().prosper_mstep(ctx.handle, C.byref(args), C.byref(accs), _ptr(W_old),
                                          _ptr(W_new), _ptr(theta_new), C.c_void_p(st)),
                ctx.handle)
+    return W_new, theta_new
+
+
+def mstep_et(acc: Dict[str, torch.Tensor], W_old: torch.Tensor, points: Dict[str, torch.Tensor],
+             *, gamma: int, model: str = "bsc", pi: float = 0.5,
+             theta: Optional[torch.Tensor] = None, W_new: Optional[torch.Tensor] = None,
+             theta_new: Optional[torch.Tensor] = None, ctx: Optional[Context] = None,
+             stream: Optional[torch.cuda.Stream] = None):
+    """The selected-points M-step (prosper_mstep_et): W_new from all points as
+    `mstep`; pi and sigma from the points with the largest logL (their count
+    from the prior's share of draws with at most `gamma` causes).  `points`
+    holds the E-step's logL, k_mean and res; the E-step's pi is `theta[0]`
+    when given, else `pi`.  Returns (W_new, theta_new)."""
+    _dev_f32("W_old", W_old)
+    D, H = W_old.shape
+    N = int(points["logL"].numel())
+    ctx = ctx or context(W_old.device.index)
+    if W_new is None:
+        W_new = torch.empty_like(W_old)
+    if theta_new is None:
+        theta_new = torch.empty(2, dtype=torch.float64, device=W_old.device)
+    args = _lib.make_args(model, "fp32", N, D, H, 1, gamma, pi=pi, theta_dev=_ptr(theta))
+    st = (stream or torch.cuda.current_stream(W_old.device)).cuda_stream
+    _lib.check(_lib.load().prosper_mstep_et(ctx.handle, C.byref(args), C.byref(_acc_struct(acc)),
+                                            _ptr(points["logL"]), _ptr(points["k_mean"]),
+                                            _ptr(points["res"]), _ptr(W_old), _ptr(W_new),
+                                            _ptr(theta_new), C.c_void_p(st)), ctx.handle)
     return W_new, theta_new

@@ -482,6 +482,11 @@ prosper_status check_estep(const prosper_args* a, const float* Y, const float* W
     *msg = "accumulate=1 needs acc->A, acc->B and acc->scal";
     return PROSPER_EINVAL;
   }
+  if (out && (out->k_mean || out->res) && a->model != PROSPER_BSC &&
+      a->model != PROSPER_TSC) {
+    *msg = "k_mean and res outputs are defined for BSC and TSC";
+    return PROSPER_EINVAL;
+  }
   if (a->accumulate && a->model == PROSPER_DSC && !acc->vcount) {
     *msg = "DSC with accumulate=1 needs acc->vcount";
     return PROSPER_EINVAL;
@@ -508,7 +513,7 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
   L.npairs = (size_t)Hp * (Hp + 1) / 2;
   L.plan = stats_plan(N, D, H, num_cu);
   L.tree_acc = L.lin_acc && a->topk == 0 && args_beta(a) == 1.0f &&
-               has_tree_kernel(a->model, Hp, a->gamma) &&
+               !(out && (out->k_mean || out->res)) && has_tree_kernel(a->model, Hp, a->gamma) &&
                (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
   L.partB_floats = L.tree_acc ? (size_t)num_cu * stats_bslice_floats() : L.plan.partB_floats;
   L.max_acc = a->accumulate && is_max_model(a->model) && has_max_tree(Hp, a->gamma, D, H);
@@ -599,7 +604,8 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);
       return launch_states_lin(model, Hp, a->gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL,
                                top_mask, top_q, a->topk, Aacc != nullptr, Bacc, scal, num_cu,
-                               &tree_blocks, s, args_beta(a));
+                               &tree_blocks, s, args_beta(a), out ? out->k_mean : nullptr,
+                               out ? out->res : nullptr);
     });
   if (e == hipSuccess && Aacc && !is_max_model(model))
     e = timed(c, "stats", s, [&] {
@@ -610,6 +616,12 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
 }
 
 }  // namespace prosper
+
+namespace {
+prosper_status mstep_entry(prosper_ctx* c, const prosper_args* a, const prosper_acc* acc,
+                           const float* W_old, float* W_new, double* theta_new, void* stream,
+                           const float* logL, const float* k_mean, const float* res);
+}  // namespace
 
 // ======================================================================= ABI
 extern "C" {
@@ -819,6 +831,34 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
 
 prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prosper_acc* acc,
                              const float* W_old, float* W_new, double* theta_new, void* stream) {
+  return mstep_entry(c, a, acc, W_old, W_new, theta_new, stream, nullptr, nullptr, nullptr);
+}
+
+prosper_status prosper_mstep_et(prosper_ctx* c, const prosper_args* a, const prosper_acc* acc,
+                                const float* logL, const float* k_mean, const float* res,
+                                const float* W_old, float* W_new, double* theta_new,
+                                void* stream) {
+  if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
+  if (!a) return fail(c, PROSPER_EINVAL, "args is NULL");
+  if (a->model != PROSPER_BSC && a->model != PROSPER_TSC)
+    return fail(c, PROSPER_EINVAL, "the selected-points M-step is defined for BSC and TSC");
+  if (a->N < 1) return fail(c, PROSPER_EINVAL, "N < 1");
+  if (a->gamma < 0) return fail(c, PROSPER_EINVAL, "gamma < 0");
+  if (!logL || !k_mean || !res) return fail(c, PROSPER_EINVAL, "logL, k_mean or res is NULL");
+  if (!a->theta_dev && !(a->pi > 0.0 && a->pi < 1.0))
+    return fail(c, PROSPER_EINVAL, "pi outside (0, 1)");
+  return mstep_entry(c, a, acc, W_old, W_new, theta_new, stream, logL, k_mean, res);
+}
+
+}  // extern "C"
+
+namespace {
+// prosper_mstep, and with logL/k_mean/res the selected-points variant: its
+// pi and sigma are formed before the M-step proper (which may overwrite the
+// E-step's pi when theta_new aliases theta_dev) and copied in after it.
+prosper_status mstep_entry(prosper_ctx* c, const prosper_args* a, const prosper_acc* acc,
+                           const float* W_old, float* W_new, double* theta_new, void* stream,
+                           const float* logL, const float* k_mean, const float* res) {
   if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
   if (!a) return fail(c, PROSPER_EINVAL, "args is NULL");
   if (a->model != PROSPER_BSC && a->model != PROSPER_TSC && a->model != PROSPER_DSC &&
@@ -840,6 +880,14 @@ prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prospe
   const bool reuse = c->factor_ready && c->factor_B == acc->B && c->factor_model == a->model &&
                      c->factor_D == a->D && c->factor_H == a->H;
   c->factor_ready = false;
+  const bool et = logL != nullptr;
+  if (et) {
+    e = timed(c, "mstep", s, [&] {
+      return launch_mstep_et_select(a->N, a->D, a->H, a->gamma, a->pi, a->theta_dev, logL,
+                                    k_mean, res, c->mwork.p, s);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "M-step launch");
+  }
   e = timed(c, "mstep", s, [&] {
     if (reuse)
       return launch_mstep_solve(a->model, a->D, a->H, acc->A, acc->B, acc->scal, W_old, W_new,
@@ -849,8 +897,10 @@ prosper_status prosper_mstep(prosper_ctx* c, const prosper_args* a, const prospe
   });
   if (e == hipSuccess && dsc)
     e = launch_mstep_dsc_prior(a->H, a->nvalues, acc->scal, acc->vcount, theta_new, s);
+  if (e == hipSuccess && et) e = launch_mstep_et_finish(a->D, a->H, c->mwork.p, theta_new, s);
   if (e != hipSuccess) return hip_fail(c, e, "M-step launch");
   return PROSPER_OK;
 }
 
-}  // extern "C"
+}  // namespace
+

@@ -41,6 +41,7 @@ struct MstepHdr {
   double trB;  // trace of B (active part)
   int failed;  // a pivot was not positive
   int pad;
+  double et_pi, et_s2;  // the selected-points variant's pi and sigma^2
 };
 
 // Workspace: header | M (H x H) | Dinv | DinvT (64 x 64 per diagonal block) |
@@ -458,6 +459,146 @@ hipError_t launch_mstep_dsc_prior(int H, int nv, const double* scal, const doubl
                                   double* theta_new, hipStream_t st) {
   hipLaunchKernelGGL(k_mstep_dsc_prior, dim3(1), dim3(64), 0, st, H, nv, scal, vcount,
                      theta_new);
+  return hipGetLastError();
+}
+
+// Selected-points M-step (prosper_mstep_et): one workgroup of 1024 threads.
+// N_cut and the truncated-prior moments A, B from the E-step's pi; the
+// N_cut-th largest logL by a radix select over order-preserving keys (four
+// 8-bit digits, most significant first, a 256-bin histogram in LDS each);
+// then the kept points' <k> and res summed in FP64, the points at the
+// threshold key taken in index order when not all of them are kept.
+__global__ __launch_bounds__(1024) void k_et_select(int64_t N, int D, int H, int gamma,
+                                                    double pi_h,
+                                                    const double* __restrict__ theta_dev,
+                                                    const float* __restrict__ logL,
+                                                    const float* __restrict__ k_mean,
+                                                    const float* __restrict__ res,
+                                                    MstepHdr* __restrict__ hdr) {
+  __shared__ unsigned int hist[256];
+  __shared__ uint32_t s_prefix;
+  __shared__ int64_t s_need, s_cnt_eq;
+  __shared__ double red_k[16], red_r[16];
+  __shared__ int wcount[16];
+  __shared__ int64_t s_taken;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double pi = theta_dev ? theta_dev[0] : pi_h;
+  // A = P(#non-zero <= gamma), B = E[#non-zero; #non-zero <= gamma]
+  double A = 0.0, B = 0.0;
+  {
+    double t = exp((double)H * log1p(-pi));  // k = 0
+    for (int k = 0; k <= gamma && k <= H; ++k) {
+      A += t;
+      B += k * t;
+      t *= (double)(H - k) / (double)(k + 1) * (pi / (1.0 - pi));
+    }
+  }
+  int64_t n_cut = llround((double)N * A);
+  n_cut = n_cut < 1 ? 1 : (n_cut > N ? N : n_cut);
+  if (tid == 0) {
+    s_prefix = 0u;
+    s_need = n_cut;
+  }
+  // radix select of the n_cut-th largest key
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int b = tid; b < 256; b += 1024) hist[b] = 0u;
+    __syncthreads();
+    const uint32_t prefix = s_prefix;
+    const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+    for (int64_t n = tid; n < N; n += 1024) {
+      const uint32_t key = f2key(logL[n]);
+      if ((key & hmask) == (prefix & hmask)) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int64_t need = s_need, above = 0;
+      int b = 255;
+      for (; b > 0; --b) {
+        if (above + (int64_t)hist[b] >= need) break;
+        above += hist[b];
+      }
+      s_need = need - above;
+      s_prefix = prefix | ((uint32_t)b << shift);
+      if (shift == 0) s_cnt_eq = hist[b];
+    }
+    __syncthreads();
+  }
+  const uint32_t T = s_prefix;
+  const int64_t need = s_need, cnt_eq = s_cnt_eq;
+  // sums over the keys above T, and over all keys at T when all are kept
+  double sk = 0.0, sr = 0.0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const uint32_t key = f2key(logL[n]);
+    if (key > T || (key == T && need == cnt_eq)) {
+      sk += (double)k_mean[n];
+      sr += (double)res[n];
+    }
+  }
+  // otherwise the first `need` points at T in index order: chunks of 1024
+  // consecutive points, a block-wide prefix count of the points at T
+  if (need < cnt_eq) {
+    if (tid == 0) s_taken = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < N; base += 1024) {
+      const int64_t n = base + tid;
+      const bool eq = n < N && f2key(logL[n]) == T;
+      const uint64_t bal = ballot64(eq);
+      if (lane == 0) wcount[wave] = __popcll(bal);
+      __syncthreads();
+      int64_t before = s_taken;
+      for (int w = 0; w < wave; ++w) before += wcount[w];
+      before += __popcll(bal & ((1ull << lane) - 1ull));
+      if (eq && before < need) {
+        sk += (double)k_mean[n];
+        sr += (double)res[n];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int64_t t = s_taken;
+        for (int w = 0; w < 16; ++w) t += wcount[w];
+        s_taken = t;
+      }
+      __syncthreads();
+    }
+  }
+  sk = wave_sum_d(sk);
+  sr = wave_sum_d(sr);
+  if (lane == 0) {
+    red_k[wave] = sk;
+    red_r[wave] = sr;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tk = 0.0, tr = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      tk += red_k[w];
+      tr += red_r[w];
+    }
+    const double kbar = tk / (double)n_cut;
+    hdr->et_pi = B > 0.0 ? pi * kbar * A / B : pi;
+    hdr->et_s2 = tr / ((double)n_cut * (double)D);
+  }
+}
+
+__global__ void k_et_finish(const MstepHdr* __restrict__ hdr, double* __restrict__ theta_new) {
+  if (threadIdx.x || blockIdx.x) return;
+  theta_new[0] = hdr->et_pi;
+  theta_new[1] = sqrt(fmax(hdr->et_s2, 0.0));
+}
+
+hipError_t launch_mstep_et_select(int64_t N, int D, int H, int gamma, double pi,
+                                  const double* theta_dev, const float* logL,
+                                  const float* k_mean, const float* res, void* work,
+                                  hipStream_t st) {
+  const MstepWork w = carve_mstep(work, D, H);
+  hipLaunchKernelGGL(k_et_select, dim3(1), dim3(1024), 0, st, N, D, H, gamma, pi, theta_dev, logL,
+                     k_mean, res, w.hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mstep_et_finish(int D, int H, void* work, double* theta_new, hipStream_t st) {
+  const MstepWork w = carve_mstep(work, D, H);
+  hipLaunchKernelGGL(k_et_finish, dim3(1), dim3(64), 0, st, w.hdr, theta_new);
   return hipGetLastError();
 }
 

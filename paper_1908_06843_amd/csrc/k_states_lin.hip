@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void k_states_generic(
     const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
     uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk,
     float* __restrict__ ss_out, float* __restrict__ B_atomic, double* __restrict__ scal,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count) {
+    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count,
+    float* __restrict__ k_out, float* __restrict__ res_out) {
   __shared__ GenLds sh[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   GenLds& S = sh[wave];
@@ -118,8 +119,8 @@ __global__ __launch_bounds__(256) void k_states_generic(
       }
     }
     const float m = wave_max(mx);
-    // pass 2: weights and moments
-    float z = 0.0f, z1 = 0.0f;
+    // pass 2: weights and moments (zl: the weighted log-joints, for res_out)
+    float z = 0.0f, z1 = 0.0f, zl = 0.0f;
     if (live) {
       for (int64_t k = lane; k < nstates; k += 64) {
         const uint32_t act = tab_act[k];
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(256) void k_states_generic(
         const float e = tempered ? fast_exp2(beta * (L - m)) : e1;
         z += e;
         z1 += e1;
+        zl = fmaf(e, L, zl);
         rem = act;
         while (rem) {
           const int j = __ffs(rem) - 1;
@@ -197,8 +199,15 @@ __global__ __launch_bounds__(256) void k_states_generic(
         }
       }
       const float kmean = wave_sum(kpart) * invZ;
+      // <||y - W s||^2> = ||y||^2 - <2 s^T b - s^T G s>, and the log-joint
+      // relative to the zero state is k c1 + lam2 (2 s^T b - s^T G s)
+      const float EL = res_out ? wave_sum(zl) * invZ : 0.0f;
       if (lane == 0) {
         if (logL) logL[n] = (float)lL;
+        if (k_out) k_out[n] = kmean;
+        if (res_out)
+          res_out[n] = (float)((double)yy[n] - ((double)EL - (double)c1 * (double)kmean) /
+                                                   (double)lam2);
         acc_k += kmean;
         acc_l += lL;
       }
@@ -277,11 +286,12 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
                              const Prepared& p, const Scratch& s, float* logL,
                              uint32_t* top_mask, float* top_q, int topk, bool acc,
                              float* acc_B, double* scal, int num_cu, int* tree_blocks,
-                             hipStream_t st, float beta) {
+                             hipStream_t st, float beta, float* k_out, float* res_out) {
   if (tree_blocks) *tree_blocks = 0;
   if (N <= 0) return hipSuccess;
   const bool tsc = (model == PROSPER_TSC);
-  if (topk == 0 && beta == 1.0f && has_tree_kernel(model, Hp, gamma)) {
+  const bool per_point = k_out || res_out;
+  if (topk == 0 && beta == 1.0f && !per_point && has_tree_kernel(model, Hp, gamma)) {
     // training: B partials inside the walk when B's packed triangle fits in LDS
     int nblk = 0;
     if (acc && (int64_t)H * (H + 1) / 2 <= stats_bslice_floats()) {
@@ -305,12 +315,12 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
         hipLaunchKernelGGL(k_states_generic<true>, dim3(32), dim3(256), 0, st, s.sel, s.bc, s.yy,
                            p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean, logL,
                            top_mask, top_q, 0, (float*)nullptr, Bat, scal, s.redo_list,
-                           s.redo_count);
+                           s.redo_count, (float*)nullptr, (float*)nullptr);
       else
         hipLaunchKernelGGL(k_states_generic<false>, dim3(32), dim3(256), 0, st, s.sel, s.bc,
                            s.yy, p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean,
                            logL, top_mask, top_q, 0, (float*)nullptr, Bat, scal, s.redo_list,
-                           s.redo_count);
+                           s.redo_count, (float*)nullptr, (float*)nullptr);
     }
     return hipGetLastError();
   }
@@ -321,12 +331,12 @@ hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int
     hipLaunchKernelGGL(k_states_generic<true>, dim3((unsigned)blocks), dim3(256), 0, st, s.sel,
                        s.bc, s.yy, p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean,
                        logL, top_mask, top_q, topk, ss_out, (float*)nullptr, scal, nullptr,
-                       nullptr);
+                       nullptr, k_out, res_out);
   else
     hipLaunchKernelGGL(k_states_generic<false>, dim3((unsigned)blocks), dim3(256), 0, st, s.sel,
                        s.bc, s.yy, p.G, H, N, Hp, nstates, tab_act, tab_sgn, p.theta, s.s_mean,
                        logL, top_mask, top_q, topk, ss_out, (float*)nullptr, scal, nullptr,
-                       nullptr);
+                       nullptr, k_out, res_out);
   return hipGetLastError();
 }
 

@@ -166,13 +166,15 @@ hipError_t launch_project_select(int model, int prec, const float* Y, int64_t N,
 // of partials in *tree_blocks), or the walk writes pair-major <s s^T> into
 // s.ss for the statistics kernel (*tree_blocks = 0).  Points handed to the
 // exact kernel add their <s s^T> straight into acc_B with atomics.
-// beta != 1 (annealing) always takes the table-driven kernel.
+// beta != 1 (annealing) and the per-point outputs k_out (<k>) and res_out
+// (<||y - W s||^2>) always take the table-driven kernel.
 hipError_t launch_states_lin(int model, int Hp, int gamma, int64_t N, int H, int64_t nstates,
                              const uint32_t* tab_act, const uint32_t* tab_sgn,
                              const Prepared& p, const Scratch& s, float* logL,
                              uint32_t* top_mask, float* top_q, int topk, bool acc,
                              float* acc_B, double* scal, int num_cu, int* tree_blocks,
-                             hipStream_t st, float beta = 1.0f);
+                             hipStream_t st, float beta = 1.0f, float* k_out = nullptr,
+                             float* res_out = nullptr);
 // Max-superposition models: MCA and MMCA share the walk, statistics and M-step.
 inline bool is_max_model(int m) { return m == PROSPER_MCA || m == PROSPER_MMCA; }
 // DSC state walk (tab_code: 3-bit value codes of the actives): compiled for
@@ -204,6 +206,13 @@ size_t mstep_workspace_bytes(int model, int D, int H);
 hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
                         const double* scal, const float* W_old, float* W_new,
                         double* theta_new, void* work, hipStream_t st);
+// Selected-points M-step: pi and sigma^2 of the kept points into the M-step
+// workspace (before the M-step proper), then copied into theta_new after it.
+hipError_t launch_mstep_et_select(int64_t N, int D, int H, int gamma, double pi,
+                                  const double* theta_dev, const float* logL,
+                                  const float* k_mean, const float* res, void* work,
+                                  hipStream_t st);
+hipError_t launch_mstep_et_finish(int D, int H, void* work, double* theta_new, hipStream_t st);
 // DSC prior update after the linear M-step: theta_new[2 + v] = pv_v.
 hipError_t launch_mstep_dsc_prior(int H, int nv, const double* scal, const double* vcount,
                                   double* theta_new, hipStream_t st);

@@ -247,10 +247,16 @@ class EM:
     statistics (at the schedule's temperature) and the FP64 M-step, both on
     the device; W, pi and sigma stay in device memory.  `lparams` holds the
     learned parameters, `logL` the per-iteration sum of the data
-    log-likelihood bound (read back only when `track_logL`)."""
+    log-likelihood bound (read back only when `track_logL`).
+    `selected_points` (BSC/TSC) takes pi and sigma from the points best
+    explained by at most gamma causes (`api.mstep_et`); W from all points."""
 
     def __init__(self, model: Model, anneal: Annealing, data: Optional[Dict] = None,
-                 lparams: Optional[Dict] = None, track_logL: bool = True, seed: int = 0):
+                 lparams: Optional[Dict] = None, track_logL: bool = True, seed: int = 0,
+                 selected_points: bool = False):
+        if selected_points and model.kind not in ("bsc", "tsc"):
+            raise ValueError("the selected-points M-step is defined for BSC and TSC")
+        self.selected_points = bool(selected_points)
         self.model = model
         self.anneal = anneal
         self.data = data
@@ -280,10 +286,15 @@ class EM:
         for it in range(self.anneal.iterations):
             beta = self.anneal.beta(it)
             api.zero_acc(acc)
-            api.estep(Y, W, Hprime=m.Hprime, gamma=m.gamma, model=m.kind,
-                      precision=m.precision, theta=theta, acc=acc, want=(), ctx=ctx,
-                      factor_b=factor_b, beta=beta, phi=m._phi())
-            api.mstep(acc, W, model=m.kind, W_new=W_next, theta_new=theta, ctx=ctx)
+            want = ("logL", "k_mean", "res") if self.selected_points else ()
+            pts = api.estep(Y, W, Hprime=m.Hprime, gamma=m.gamma, model=m.kind,
+                            precision=m.precision, theta=theta, acc=acc, want=want, ctx=ctx,
+                            factor_b=factor_b, beta=beta, phi=m._phi())
+            if self.selected_points:
+                api.mstep_et(acc, W, pts, gamma=m.gamma, model=m.kind, theta=theta,
+                             W_new=W_next, theta_new=theta, ctx=ctx)
+            else:
+                api.mstep(acc, W, model=m.kind, W_new=W_next, theta_new=theta, ctx=ctx)
             W, W_next = W_next, W
             eps = self.anneal.noise(it)
             if eps > 0.0:

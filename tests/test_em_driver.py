@@ -38,3 +38,9 @@ def test_dsc_model_checks_its_value_set():
         em.DSC_ET(16, 8, 4, 2, (1.0, 2.0), device=0)
     with pytest.raises(ValueError):
         em.DSC_ET(16, 8, 4, 2, (0.0,), device=0)
+
+
+def test_selected_points_needs_a_linear_model():
+    from paper_1908_06843_amd import em
+    with pytest.raises(ValueError):
+        em.EM(em.MCA_ET(16, 8, 4, 2, device=0), LinearAnnealing(2), selected_points=True)
