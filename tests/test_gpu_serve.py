@@ -176,7 +176,9 @@ def test_serving_other_models_match_oracle(model, name, Hp, gamma):
 def test_wait_stages_add_up():
     """The stage split of prosper_serve_wait_stages: all stages >= 0, the
     host stages add up to the total, the batch's GPU time fits in the span
-    between its launch and the completion seen."""
+    from the start of its launch calls (its first event is recorded before
+    the rest of the launch is issued, so the GPU may start meanwhile) to the
+    completion seen."""
     from paper_1908_06843_amd.serve import Server
     wl, g, W = _dictionary()
     srv = Server(W, wl.pi, wl.sigma, precision="bf16", mem_budget_bytes=32 << 20)
@@ -188,6 +190,6 @@ def test_wait_stages_add_up():
             assert all(v >= 0.0 for v in st.values())
             host = st["queue"] + st["launch"] + st["device_span"] + st["delivery"]
             assert abs(host - st["total"]) <= 1e-3 + 1e-6 * st["total"]
-            assert 0.0 < st["gpu"] <= st["device_span"] + 0.05
+            assert 0.0 < st["gpu"] <= st["launch"] + st["device_span"] + 0.05
     finally:
         srv.stop()
