@@ -317,17 +317,23 @@ __global__ __launch_bounds__(64) void k_states_tree(
 // into a workgroup-private copy of B's packed upper triangle in LDS, then
 // store that partial with plain stores (partB[block]); the partials are
 // summed by the statistics reduction.  Requires H (H + 1) / 2 <= BSLICE floats.
+// The LDS copy is fixed point: every term <s_i s_j> lies in [-1, 1] and a
+// workgroup adds at most `ppw` of them per entry, so with the quantum
+// 1/qscale, qscale = 2^k and ppw 2^k < 2^30, the int32 sums cannot overflow;
+// each term is rounded to within 2^-(k+1) (about 5e-7 at k = 20, below the
+// terms' own FP32 rounding relative to the sums they enter).  Integer LDS
+// atomics run at plain-LDS speed where FP32 LDS atomics do not.
 template <int HP, int GAMMA, bool TSC>
 __global__ __launch_bounds__(512) void k_states_tree_acc(
     const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
     const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
     float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ partB,
     int64_t part_stride, double* __restrict__ scal, int32_t* __restrict__ redo_list,
-    int32_t* __restrict__ redo_count) {
-  extern __shared__ float Bl[];  // packed upper triangle, row h at h H - h (h - 1) / 2
+    int32_t* __restrict__ redo_count, float qscale) {
+  extern __shared__ int Bl[];  // packed upper triangle, row h at h H - h (h - 1) / 2
   __shared__ double red[2][8];
   const int len = H * (H + 1) / 2;
-  for (int e = threadIdx.x; e < len; e += 512) Bl[e] = 0.0f;
+  for (int e = threadIdx.x; e < len; e += 512) Bl[e] = 0;
   __syncthreads();
   double a0 = 0.0, a1 = 0.0;
   for (int64_t base = (int64_t)blockIdx.x * 512; base < N; base += (int64_t)gridDim.x * 512) {
@@ -343,9 +349,10 @@ __global__ __launch_bounds__(512) void k_states_tree_acc(
       for (int i = 0; i < HP; ++i) {
         const int hi = R.s[i];
         const int row = hi * H - hi * (hi - 1) / 2 - hi;  // packed index of (hi, h2) = row + h2
-        atomicAdd(&Bl[row + hi], R.K2[i] * R.invZ);
+        atomicAdd(&Bl[row + hi], __float2int_rn(R.K2[i] * R.invZ * qscale));
 #pragma unroll
-        for (int j = i + 1; j < HP; ++j) atomicAdd(&Bl[row + R.s[j]], R.P[i][j] * R.invZ);
+        for (int j = i + 1; j < HP; ++j)
+          atomicAdd(&Bl[row + R.s[j]], __float2int_rn(R.P[i][j] * R.invZ * qscale));
       }
       a0 += (double)R.kmean;
       a1 += R.lL;
@@ -353,7 +360,8 @@ __global__ __launch_bounds__(512) void k_states_tree_acc(
   }
   __syncthreads();
   float* out = partB + (int64_t)blockIdx.x * part_stride;
-  for (int e = threadIdx.x; e < len; e += 512) out[e] = Bl[e];
+  const double unq = 1.0 / (double)qscale;
+  for (int e = threadIdx.x; e < len; e += 512) out[e] = (float)((double)Bl[e] * unq);
   if (scal) {
     a0 = wave_sum_d(a0);
     a1 = wave_sum_d(a1);
@@ -382,13 +390,18 @@ __global__ __launch_bounds__(512) void k_states_tree_acc(
                                                 int acc_blocks, float* partB, int64_t stride,    \
                                                 hipStream_t st) {                                \
     if (acc_blocks > 0) {                                                                        \
+      /* fixed-point quantum: at most ppw points per workgroup, ppw 2^k < 2^30 */                \
+      const int64_t ppw = (N + (int64_t)acc_blocks * 512 - 1) / ((int64_t)acc_blocks * 512) * 512; \
+      int k = 0;                                                                                 \
+      while (k < 30 && ((int64_t)ppw << (k + 1)) < ((int64_t)1 << 30)) ++k;                     \
+      const float qscale = (float)((int64_t)1 << k);                                             \
       auto kern = k_states_tree_acc<HPV, GMV, TSCV>;                                             \
       const size_t lds = (size_t)H * (H + 1) / 2 * 4;                                            \
       hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);              \
       if (e != hipSuccess) return e;                                                             \
       hipLaunchKernelGGL(kern, dim3((unsigned)acc_blocks), dim3(512), lds, st, s.sel, s.bc,      \
                          s.yy, p.G, H, N, p.theta, s.s_mean, logL, partB, stride, scal,          \
-                         s.redo_list, s.redo_count);                                             \
+                         s.redo_list, s.redo_count, qscale);                                     \
       return hipGetLastError();                                                                  \
     }                                                                                            \
     hipLaunchKernelGGL((k_states_tree<HPV, GMV, TSCV>), dim3((unsigned)((N + 63) / 64)),         \
