@@ -17,12 +17,13 @@
 // workspace header and leaves W unchanged.
 //   k_ms_panel : right-looking blocked Cholesky B = L L^T with 64-column
 //                panels.  Every workgroup factors the 64 x 64 diagonal block
-//                in one wave's registers (lane i holds row i) and inverts it
-//                (lane j forms column j of L_kk^-1), then forms 256 of the
-//                rows below as products with L_kk^-T.  L is written to the
-//                lower triangle and mirrored into the upper one, and the
-//                block inverses are kept (row-major and transposed), so that
-//                both substitutions of the solve read coalesced rows;
+//                in one wave's registers (lane i holds row i), then solves
+//                256 of the rows below against it by forward substitution,
+//                one thread per row.  L is written to the lower triangle and
+//                mirrored into the upper one, so that both substitutions of
+//                the solve read coalesced rows;
+//   k_ms_invdiag: after the last panel, the inverses of all diagonal blocks
+//                at once (row-major and transposed), for the solve;
 //   k_ms_syrk  : trailing update T -= P P^T on 32 x 32 tiles;
 //   k_ms_solve : one wave per pixel d: block forward and backward
 //                substitution of x, each block step a few matrix-vector
@@ -143,20 +144,18 @@ __device__ __forceinline__ void factor_rows(double (&a)[NBK], int lane, double* 
 }
 
 // Panel at kb (nb = min(64, H - kb) columns): factor the diagonal block
-// L_kk, invert it (column j of L_kk^-1 by forward substitution down the
-// rows, one lane per column), then form the rows below as
-// L[i, kb:kb+nb] = M[i, kb:kb+nb] L_kk^-T, a product with no dependent
-// chain.  Every workgroup factors the (small) diagonal block itself and
-// solves 256 of the rows below; workgroup 0 writes the block, its mirror,
-// L_kk^-1 (row-major and transposed) and nothing else.  Each row below is
-// written to the lower triangle and mirrored into the upper one, so that
-// both substitutions of the solve read coalesced rows.
+// L_kk in one wave's registers, then solve this workgroup's 256 rows below,
+// L[i, kb:kb+nb] L_kk^T = M[i, kb:kb+nb], by forward substitution, one
+// thread per row (the rows' chains run side by side).  Every workgroup
+// factors the (small) diagonal block itself; workgroup 0 writes the block and
+// its mirror.  Each row below is written to the lower triangle and mirrored
+// into the upper one, so that both substitutions of the solve read coalesced
+// rows.  The inverses of the diagonal blocks, which only the solve needs, are
+// formed afterwards for all blocks at once (k_ms_invdiag), off the chain of
+// panels.
 __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restrict__ M,
-                                                  double* __restrict__ Dinv,
-                                                  double* __restrict__ DinvT,
                                                   MstepHdr* __restrict__ hdr) {
   __shared__ double Ls[NB][NB + 1];  // L_kk, row-major (lower)
-  __shared__ double Xs[NB][NB + 1];  // L_kk^-1, row-major (lower)
   __shared__ double inv_s[NB];
   __shared__ double colb[NB];
   const int nb = min(NB, H - kb);
@@ -182,29 +181,7 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     if (blockIdx.x == 0 && bad && lane == 0) hdr->failed = 1;
   }
   __syncthreads();
-  if (tid < 64) {
-    // x[i] = (L_kk^-1)[i][lane]: (delta_i,lane - sum_{m<i} L[i][m] x[m]) / L[i][i]
-    double x[NB];
-    static_for<0, NB>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      __builtin_amdgcn_sched_barrier(0);
-      double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
-      static_for<0, i>([&](auto mc) {
-        constexpr int m = decltype(mc)::value;
-        if constexpr ((m & 1) == 0) s0 = fma(-Ls[i][m], x[m], s0);
-        else s1 = fma(-Ls[i][m], x[m], s1);
-      });
-      x[i] = (s0 + s1) * inv_s[i];
-    });
-    __builtin_amdgcn_sched_barrier(0);
-    static_for<0, NB>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      Xs[i][lane] = x[i];
-    });
-  }
-  __syncthreads();
   if (blockIdx.x == 0) {
-    const int blk = kb / NB;
     for (int e = tid; e < NB * NB; e += 256) {
       const int r = e >> 6, c = e & 63;
       if (r < nb && c <= r) {
@@ -212,8 +189,6 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
         M[(int64_t)(kb + r) * H + kb + c] = v;
         M[(int64_t)(kb + c) * H + kb + r] = v;
       }
-      Dinv[(int64_t)blk * NB * NB + e] = Xs[r][c];
-      DinvT[(int64_t)blk * NB * NB + e] = Xs[c][r];
     }
   }
   // rows below the block exist only when the block is full (nb == 64)
@@ -225,24 +200,65 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     constexpr int c = decltype(cc)::value;
     x[c] = xp[c];
   });
-  // L[i][c] = sum_{m <= c} M[i][m] (L_kk^-1)[c][m], highest c first so that
-  // each result can replace its input (smaller c read only m <= c)
-  static_for<0, NB>([&](auto cr) {
-    constexpr int c = NB - 1 - decltype(cr)::value;
+  // x_c = (M[i][c] - sum_{m<c} L[c][m] x_m) / L[c][c]
+  static_for<0, NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
     __builtin_amdgcn_sched_barrier(0);
-    double s0 = 0.0, s1 = 0.0;
-    static_for<0, c + 1>([&](auto mc) {
+    double s0 = x[c], s1 = 0.0;
+    static_for<0, c>([&](auto mc) {
       constexpr int m = decltype(mc)::value;
-      if constexpr ((m & 1) == 0) s0 = fma(x[m], Xs[c][m], s0);
-      else s1 = fma(x[m], Xs[c][m], s1);
+      if constexpr ((m & 1) == 0) s0 = fma(-Ls[c][m], x[m], s0);
+      else s1 = fma(-Ls[c][m], x[m], s1);
     });
-    x[c] = s0 + s1;
+    x[c] = (s0 + s1) * inv_s[c];
   });
   __builtin_amdgcn_sched_barrier(0);
   static_for<0, NB>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     xp[c] = x[c];
     M[(int64_t)(kb + c) * H + i] = x[c];
+  });
+}
+
+// The inverses of the diagonal blocks of L (one workgroup of one wave per
+// block, all blocks at once): column j of L_bb^-1 by forward substitution
+// down the rows, lane j; written row-major (Dinv) and transposed (DinvT).
+// Padding rows and columns of a last partial block are the identity.
+__global__ __launch_bounds__(64) void k_ms_invdiag(int H, const double* __restrict__ M,
+                                                   double* __restrict__ Dinv,
+                                                   double* __restrict__ DinvT) {
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double inv_s[NB];
+  const int b = blockIdx.x, kb = b * NB, nb = min(NB, H - kb);
+  const int lane = threadIdx.x;
+  {
+    const double* rp = M + (int64_t)min(kb + lane, H - 1) * H + kb;
+    static_for<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      const double v = rp[c < nb ? c : 0];
+      Ls[lane][c] = (lane < nb && c < nb) ? ((c <= lane) ? v : 0.0) : (c == lane ? 1.0 : 0.0);
+    });
+  }
+  __syncthreads();
+  inv_s[lane] = 1.0 / Ls[lane][lane];
+  __syncthreads();
+  double x[NB];
+  static_for<0, NB>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    __builtin_amdgcn_sched_barrier(0);
+    double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+    static_for<0, i>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      if constexpr ((m & 1) == 0) s0 = fma(-Ls[i][m], x[m], s0);
+      else s1 = fma(-Ls[i][m], x[m], s1);
+    });
+    x[i] = (s0 + s1) * inv_s[i];
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  static_for<0, NB>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    Dinv[(int64_t)b * NB * NB + i * NB + lane] = x[i];   // Dinv[i][lane] = Linv[i][lane]
+    DinvT[(int64_t)b * NB * NB + lane * NB + i] = x[i];  // DinvT[lane][i]
   });
 }
 
@@ -624,14 +640,15 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
     const int nb = (H - kb < NB) ? H - kb : NB;
     const int below = H - kb - nb;
     const unsigned nblk = below > 0 ? (unsigned)((below + 255) / 256) : 1u;
-    hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.Dinv, w.DinvT,
-                       w.hdr);
+    hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.hdr);
     if (below > 0) {
       const int nt = (below + 31) / 32;
       hipLaunchKernelGGL(k_ms_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, H, kb,
                          w.M);
     }
   }
+  hipLaunchKernelGGL(k_ms_invdiag, dim3((unsigned)((H + NB - 1) / NB)), dim3(64), 0, st, H, w.M,
+                     w.Dinv, w.DinvT);
   return hipGetLastError();
 }
 
