@@ -18,7 +18,7 @@
 //   k_ms_panel : right-looking blocked Cholesky B = L L^T with 64-column
 //                panels.  Every workgroup factors the 64 x 64 diagonal block
 //                in one wave's registers (lane i holds row i), then solves
-//                256 of the rows below against it by forward substitution,
+//                64 of the rows below against it by forward substitution,
 //                one thread per row.  L is written to the lower triangle and
 //                mirrored into the upper one, so that both substitutions of
 //                the solve read coalesced rows;
@@ -144,7 +144,7 @@ __device__ __forceinline__ void factor_rows(double (&a)[NBK], int lane, double* 
 }
 
 // Panel at kb (nb = min(64, H - kb) columns): factor the diagonal block
-// L_kk in one wave's registers, then solve this workgroup's 256 rows below,
+// L_kk in one wave's registers, then solve this workgroup's 64 rows below,
 // L[i, kb:kb+nb] L_kk^T = M[i, kb:kb+nb], by forward substitution, one
 // thread per row (the rows' chains run side by side).  Every workgroup
 // factors the (small) diagonal block itself; workgroup 0 writes the block and
@@ -191,8 +191,11 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
       }
     }
   }
-  // rows below the block exist only when the block is full (nb == 64)
-  const int i = kb + nb + blockIdx.x * 256 + tid;
+  // rows below the block exist only when the block is full (nb == 64); one
+  // wave of them per workgroup (more waves sharing the broadcast reads of L
+  // lengthened every row's chain)
+  if (tid >= 64) return;
+  const int i = kb + nb + blockIdx.x * 64 + tid;
   if (i >= H) return;
   double* xp = M + (int64_t)i * H + kb;
   double x[NB];
@@ -630,16 +633,16 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
   const MstepWork w = carve_mstep(work, D, H);
   hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(1024), 0, st, H, B, w.hdr);
   const int64_t HH = (int64_t)H * H;
-  // at most 16 workgroups: when B is factored beside the A statistics only
+  // at most 32 workgroups: when B is factored beside the A statistics only
   // the CUs those leave out are free, and more workgroups than fit there
   // wait for the statistics to end
   int64_t lb = (HH + 2047) / 2048;
-  if (lb > 16) lb = 16;
+  if (lb > 32) lb = 32;
   hipLaunchKernelGGL(k_ms_load, dim3((unsigned)lb), dim3(256), 0, st, H, B, w.hdr, w.M);
   for (int kb = 0; kb < H; kb += NB) {
     const int nb = (H - kb < NB) ? H - kb : NB;
     const int below = H - kb - nb;
-    const unsigned nblk = below > 0 ? (unsigned)((below + 255) / 256) : 1u;
+    const unsigned nblk = below > 0 ? (unsigned)((below + 63) / 64) : 1u;
     hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.hdr);
     if (below > 0) {
       const int nt = (below + 31) / 32;
