@@ -513,7 +513,9 @@ EstepLayout plan_estep(const prosper_args* a, const prosper_point_out* out, int 
   L.npairs = (size_t)Hp * (Hp + 1) / 2;
   L.plan = stats_plan(N, D, H, num_cu);
   L.tree_acc = L.lin_acc && a->topk == 0 && args_beta(a) == 1.0f &&
-               !(out && (out->k_mean || out->res)) && has_tree_kernel(a->model, Hp, a->gamma) &&
+               !(out && (out->k_mean || out->res)) &&
+               (has_tree_kernel(a->model, Hp, a->gamma) ||
+                (a->model == PROSPER_DSC && has_dsc_tree(Hp, a->gamma))) &&
                (int64_t)H * (H + 1) / 2 <= stats_bslice_floats();
   L.partB_floats = L.tree_acc ? (size_t)num_cu * stats_bslice_floats() : L.plan.partB_floats;
   L.max_acc = a->accumulate && is_max_model(a->model) && has_max_tree(Hp, a->gamma, D, H);
@@ -598,7 +600,8 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
       if (model == PROSPER_DSC)
         return launch_states_dsc(Hp, a->gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL,
                                  top_mask, top_q, a->topk, Aacc != nullptr,
-                                 Aacc ? acc->vcount : nullptr, scal, s, args_beta(a));
+                                 Aacc ? acc->vcount : nullptr, scal, s, args_beta(a), num_cu,
+                                 &tree_blocks, Bacc);
       if (is_max_model(model))
         return launch_states_max(model, Hp, a->gamma, N, D, Dp, H, ns, tab_act, Y, p, sc, logL,
                                  top_mask, top_q, a->topk, Aacc, Bacc, scal, s);

@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void k_states_dsc(
     const Theta* __restrict__ th, float* __restrict__ s_mean, float* __restrict__ logL,
     uint32_t* __restrict__ top_mask, float* __restrict__ top_q, int topk,
     float* __restrict__ ss_out, double* __restrict__ vcount, double* __restrict__ scal,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count) {
+    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count,
+    float* __restrict__ B_atomic) {
   __shared__ DscLds sh[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   DscLds& S = sh[wave];
@@ -177,6 +178,18 @@ __global__ __launch_bounds__(256) void k_states_dsc(
         }
         s_mean[n * Hp + j] = m1 * invZ;
         if (ss_out) ss_out[(int64_t)j * N + n] = m2 * invZ;
+        if (B_atomic) {
+          const int sj = sel[n * Hp + j];
+          atomicAdd(&B_atomic[(int64_t)sj * H + sj], m2 * invZ);
+        }
+      }
+      if (B_atomic) {  // few points (the compiled walk's redo list): direct adds
+        for (int idx = lane; idx < Hp * Hp; idx += 64) {
+          const int i = idx / Hp, j = idx % Hp;
+          if (i < j)
+            atomicAdd(&B_atomic[(int64_t)sel[n * Hp + i] * H + sel[n * Hp + j]],
+                      S.P[i * 32 + j] * invZ);
+        }
       }
       if (ss_out) {  // pairs i < j in row-major order after the diagonal
         for (int idx = lane; idx < Hp * Hp; idx += 64) {
@@ -406,19 +419,29 @@ struct DscTree {
   }
 };
 
-// One lane per point, 64-lane workgroups.  Pivot m = the max over the states
-// with at most two actives (a lower bound of the max: those weights are <= 1
-// and Z >= 1); a point whose Z could have overflowed (>= 2^64) is handed to
-// the table-driven kernel through the redo list and written by it.
+// Everything one lane does for one point of the compiled walk.  Pivot m =
+// the max over the states with at most two actives (a lower bound of the
+// max: those weights are <= 1 and Z >= 1); a point whose Z could have
+// overflowed (>= 2^64) is handed to the table-driven kernel through the redo
+// list (ok = false) and written by it.
 template <int HP, int GAMMA>
-__global__ __launch_bounds__(64) void k_states_dsc_tree(
-    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
-    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
-    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ ss_out,
-    double* __restrict__ vcount, double* __restrict__ scal, int32_t* __restrict__ redo_list,
-    int32_t* __restrict__ redo_count) {
-  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool live = n < N;
+struct DscPoint {
+  float M[HP], K2[HP], P[HP][HP], VC[DSC_MAXV];
+  int s[HP];
+  float invZ;
+  double lL;
+  bool ok;
+};
+
+template <int HP, int GAMMA>
+__device__ __forceinline__ void dsc_tree_point(DscPoint<HP, GAMMA>& R, int64_t n, bool live,
+                                               const int32_t* __restrict__ sel,
+                                               const float* __restrict__ bc,
+                                               const float* __restrict__ yy,
+                                               const float* __restrict__ G, int H, int64_t N,
+                                               const Theta* __restrict__ th,
+                                               int32_t* __restrict__ redo_list,
+                                               int32_t* __restrict__ redo_count) {
   const int64_t nn = live ? n : N - 1;
   const float lam2 = th->lam2;
   DscCtx<HP> C;
@@ -429,62 +452,79 @@ __global__ __launch_bounds__(64) void k_states_dsc_tree(
     C.ph[v] = th->phi[v];
     C.c[v] = th->u2[v];
   }
-  int s[HP];
 #pragma unroll
   for (int j = 0; j < HP; ++j) {
-    s[j] = sel[nn * HP + j];
+    R.s[j] = sel[nn * HP + j];
     C.b2[j] = 2.0f * lam2 * bc[nn * HP + j];
-    C.g[j] = lam2 * G[(int64_t)s[j] * H + s[j]];
+    C.g[j] = lam2 * G[(int64_t)R.s[j] * H + R.s[j]];
   }
 #pragma unroll
   for (int i = 0; i < HP; ++i)
 #pragma unroll
-    for (int j = i + 1; j < HP; ++j) C.p[i][j] = -2.0f * lam2 * G[(int64_t)s[i] * H + s[j]];
-  float M[HP], K2[HP], P[HP][HP], VC[DSC_MAXV], f0[HP], a0[GAMMA + 1];
+    for (int j = i + 1; j < HP; ++j) C.p[i][j] = -2.0f * lam2 * G[(int64_t)R.s[i] * H + R.s[j]];
+  float f0[HP], a0[GAMMA + 1];
 #pragma unroll
   for (int i = 0; i < HP; ++i) {
-    M[i] = 0.0f;
-    K2[i] = 0.0f;
+    R.M[i] = 0.0f;
+    R.K2[i] = 0.0f;
     f0[i] = 0.0f;
 #pragma unroll
-    for (int j = i + 1; j < HP; ++j) P[i][j] = 0.0f;
+    for (int j = i + 1; j < HP; ++j) R.P[i][j] = 0.0f;
   }
 #pragma unroll
-  for (int v = 0; v < DSC_MAXV; ++v) VC[v] = 0.0f;
+  for (int v = 0; v < DSC_MAXV; ++v) R.VC[v] = 0.0f;
 #pragma unroll
   for (int d = 0; d <= GAMMA; ++d) a0[d] = 0.0f;
   float m = 0.0f;  // the zero state has lj = 0
   constexpr int GPIV = GAMMA < 2 ? GAMMA : 2;
   DscTree<HP, GPIV, 0u, -1, 0>::walk1(C, f0, 0.0f, m);
-  const float Z = exp2_fast(-m) + DscTree<HP, GAMMA, 0u, -1, 0>::walk2(C, f0, a0, 0.0f, m, M, K2,
-                                                                        P, VC);
-  bool ok = live;
+  const float Z = exp2_fast(-m) + DscTree<HP, GAMMA, 0u, -1, 0>::walk2(C, f0, a0, 0.0f, m, R.M,
+                                                                        R.K2, R.P, R.VC);
+  R.ok = live;
   if (GAMMA > 2 && live && !(Z < 1.8446744e19f)) {
-    ok = false;
+    R.ok = false;
     redo_list[atomicAdd(redo_count, 1)] = (int32_t)n;
   }
-  const float invZ = 1.0f / Z;
-  const double lL = th->c0 - (double)th->lam * (double)yy[nn] +
-                    0.6931471805599453 * ((double)m + (double)log2f(Z));
-  float km = 0.0f;
-  if (ok) {
-    if (logL) logL[n] = (float)lL;
+  // fresh copies of the latent indices (keeps the G-gather offsets from being
+  // held across the walk for reuse after it)
 #pragma unroll
-    for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = M[j] * invZ;
+  for (int j = 0; j < HP; ++j) asm volatile("" : "+v"(R.s[j]));
+  R.invZ = 1.0f / Z;
+  R.lL = th->c0 - (double)th->lam * (double)yy[nn] +
+         0.6931471805599453 * ((double)m + (double)log2f(Z));
+}
+
+// One lane per point, 64-lane workgroups; optional pair-major <s s^T>.
+template <int HP, int GAMMA>
+__global__ __launch_bounds__(64) void k_states_dsc_tree(
+    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
+    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
+    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ ss_out,
+    double* __restrict__ vcount, double* __restrict__ scal, int32_t* __restrict__ redo_list,
+    int32_t* __restrict__ redo_count) {
+  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  DscPoint<HP, GAMMA> R;
+  dsc_tree_point<HP, GAMMA>(R, n, n < N, sel, bc, yy, G, H, N, th, redo_list, redo_count);
+  const float invZ = R.invZ;
+  float km = 0.0f;
+  if (R.ok) {
+    if (logL) logL[n] = (float)R.lL;
+#pragma unroll
+    for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = R.M[j] * invZ;
     if (ss_out) {  // pair-major: diagonal first, then i < j row-major
       int q = HP;
 #pragma unroll
       for (int i = 0; i < HP; ++i) {
-        ss_out[(int64_t)i * N + n] = K2[i] * invZ;
+        ss_out[(int64_t)i * N + n] = R.K2[i] * invZ;
 #pragma unroll
-        for (int j = i + 1; j < HP; ++j) ss_out[(int64_t)(q++) * N + n] = P[i][j] * invZ;
+        for (int j = i + 1; j < HP; ++j) ss_out[(int64_t)(q++) * N + n] = R.P[i][j] * invZ;
       }
     }
 #pragma unroll
-    for (int v = 1; v < DSC_MAXV; ++v) km += VC[v];
+    for (int v = 1; v < DSC_MAXV; ++v) km += R.VC[v];
   }
   if (scal) {
-    double k0 = ok ? (double)(km * invZ) : 0.0, l0 = ok ? lL : 0.0;
+    double k0 = R.ok ? (double)(km * invZ) : 0.0, l0 = R.ok ? R.lL : 0.0;
     k0 = wave_sum_d(k0);
     l0 = wave_sum_d(l0);
     if (threadIdx.x == 0) {
@@ -493,42 +533,149 @@ __global__ __launch_bounds__(64) void k_states_dsc_tree(
     }
   }
   if (vcount) {
+    const int nv = th->nv;
 #pragma unroll
     for (int v = 1; v < DSC_MAXV; ++v) {
-      if (v < C.nv) {
-        const double t = wave_sum_d(ok ? (double)(VC[v] * invZ) : 0.0);
+      if (v < nv) {
+        const double t = wave_sum_d(R.ok ? (double)(R.VC[v] * invZ) : 0.0);
         if (threadIdx.x == 0) atomicAdd(&vcount[v], t);
       }
     }
   }
 }
 
+// Training variant: persistent 512-lane workgroups that add every point's
+// <s s^T> block into a workgroup-private copy of B's packed upper triangle in
+// LDS, as int32 fixed point (every term lies within max phi_v^2 in
+// magnitude; a workgroup adds at most ppw terms per entry; the quantum
+// 1/qscale, qscale = 2^k, keeps ppw max phi^2 2^k below 2^30), then store
+// that partial with plain stores (partB[block]) for the statistics reduction.
+// Requires H (H + 1) / 2 <= the partial's length.
+template <int HP, int GAMMA>
+__global__ __launch_bounds__(512) void k_states_dsc_tree_acc(
+    const int32_t* __restrict__ sel, const float* __restrict__ bc, const float* __restrict__ yy,
+    const float* __restrict__ G, int H, int64_t N, const Theta* __restrict__ th,
+    float* __restrict__ s_mean, float* __restrict__ logL, float* __restrict__ partB,
+    int64_t part_stride, double* __restrict__ vcount, double* __restrict__ scal,
+    int32_t* __restrict__ redo_list, int32_t* __restrict__ redo_count) {
+  extern __shared__ int Bq[];  // packed upper triangle, row h at h H - h (h - 1) / 2
+  __shared__ double red[2 + DSC_MAXV][8];
+  const int len = H * (H + 1) / 2;
+  for (int e = threadIdx.x; e < len; e += 512) Bq[e] = 0;
+  const int64_t ppw = (N + (int64_t)gridDim.x * 512 - 1) / ((int64_t)gridDim.x * 512) * 512;
+  const double bound = (double)ppw * (double)th->phimax * (double)th->phimax;
+  int k = 0;
+  while (k < 30 && bound * (double)(1ll << (k + 1)) < 1073741824.0) ++k;
+  const float qscale = (float)(1ll << k);
+  const int nv = th->nv;
+  __syncthreads();
+  double a0 = 0.0, a1 = 0.0, av[DSC_MAXV];
+#pragma unroll
+  for (int v = 0; v < DSC_MAXV; ++v) av[v] = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * 512; base < N; base += (int64_t)gridDim.x * 512) {
+    const int64_t n = base + threadIdx.x;
+    DscPoint<HP, GAMMA> R;
+    dsc_tree_point<HP, GAMMA>(R, n, n < N, sel, bc, yy, G, H, N, th, redo_list, redo_count);
+    if (R.ok) {
+      const float invZ = R.invZ;
+      if (logL) logL[n] = (float)R.lL;
+#pragma unroll
+      for (int j = 0; j < HP; ++j) s_mean[n * HP + j] = R.M[j] * invZ;
+      const float qz = invZ * qscale;
+#pragma unroll
+      for (int i = 0; i < HP; ++i) {
+        const int hi = R.s[i];
+        const int row = hi * H - hi * (hi - 1) / 2 - hi;  // packed index of (hi, h2) = row + h2
+        atomicAdd(&Bq[row + hi], __float2int_rn(R.K2[i] * qz));
+#pragma unroll
+        for (int j = i + 1; j < HP; ++j) atomicAdd(&Bq[row + R.s[j]], __float2int_rn(R.P[i][j] * qz));
+      }
+      float km = 0.0f;
+#pragma unroll
+      for (int v = 1; v < DSC_MAXV; ++v) {
+        km += R.VC[v];
+        av[v] += (double)(R.VC[v] * invZ);
+      }
+      a0 += (double)(km * invZ);
+      a1 += R.lL;
+    }
+  }
+  __syncthreads();
+  float* out = partB + (int64_t)blockIdx.x * part_stride;
+  const double unq = 1.0 / (double)qscale;
+  for (int e = threadIdx.x; e < len; e += 512) out[e] = (float)((double)Bq[e] * unq);
+  // FP64 sums of the workgroup: <k>, logL and the value counts
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  a0 = wave_sum_d(a0);
+  a1 = wave_sum_d(a1);
+  if (lane == 0) {
+    red[0][w] = a0;
+    red[1][w] = a1;
+  }
+#pragma unroll
+  for (int v = 1; v < DSC_MAXV; ++v) {
+    const double t = wave_sum_d(av[v]);
+    if (lane == 0) red[2 + v][w] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 + DSC_MAXV) {
+    const int r = threadIdx.x;
+    double t = 0.0;
+    for (int q = 0; q < 8; ++q) t += red[r][q];
+    if (r < 2) {
+      if (scal) atomicAdd(&scal[r], t);
+    } else if (r >= 3 && r - 2 < nv && vcount) {
+      atomicAdd(&vcount[r - 2], t);
+    }
+  }
+}
+
 // Shapes with a compiled DSC walk (any V).
-static bool has_dsc_tree(int Hp, int gamma) { return Hp == 8 && gamma == 3; }
+bool has_dsc_tree(int Hp, int gamma) { return Hp == 8 && gamma == 3; }
 
 hipError_t launch_states_dsc(int Hp, int gamma, int64_t N, int H, int64_t nstates,
                              const uint32_t* tab_act, const uint32_t* tab_code, const Prepared& p,
                              const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, bool acc, double* vcount, double* scal, hipStream_t st,
-                             float beta) {
+                             float beta, int num_cu, int* tree_blocks, float* acc_B) {
+  if (tree_blocks) *tree_blocks = 0;
   if (N <= 0) return hipSuccess;
-  float* ss_out = acc ? s.ss : nullptr;
   double* vc = acc ? vcount : nullptr;
   if (topk == 0 && beta == 1.0f && has_dsc_tree(Hp, gamma)) {
-    hipLaunchKernelGGL((k_states_dsc_tree<8, 3>), dim3((unsigned)((N + 63) / 64)), dim3(64), 0,
-                       st, s.sel, s.bc, s.yy, p.G, H, N, p.theta, s.s_mean, logL, ss_out, vc,
-                       scal, s.redo_list, s.redo_count);
-    // points whose weights could overflow with the pivot: the table-driven kernel
+    // training: B partials inside the walk when B's packed triangle fits
+    int nblk = 0;
+    if (acc && (int64_t)H * (H + 1) / 2 <= stats_bslice_floats()) {
+      const int64_t want = (N + 511) / 512;
+      nblk = (int)(want < num_cu ? want : num_cu);
+      if (tree_blocks) *tree_blocks = nblk;
+    }
+    if (nblk > 0) {
+      auto kern = k_states_dsc_tree_acc<8, 3>;
+      const size_t lds = (size_t)H * (H + 1) / 2 * 4;
+      hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(kern), lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(512), lds, st, s.sel, s.bc, s.yy, p.G,
+                         H, N, p.theta, s.s_mean, logL, s.partB,
+                         (int64_t)stats_bslice_floats(), vc, scal, s.redo_list, s.redo_count);
+    } else {
+      hipLaunchKernelGGL((k_states_dsc_tree<8, 3>), dim3((unsigned)((N + 63) / 64)), dim3(64), 0,
+                         st, s.sel, s.bc, s.yy, p.G, H, N, p.theta, s.s_mean, logL,
+                         acc ? s.ss : nullptr, vc, scal, s.redo_list, s.redo_count);
+    }
+    // points whose weights could overflow with the pivot: the table-driven
+    // kernel (with the B partials, their <s s^T> goes straight into acc_B)
     hipLaunchKernelGGL(k_states_dsc, dim3(32), dim3(256), 0, st, s.sel, s.bc, s.yy, p.G, H, N,
                        Hp, nstates, tab_act, tab_code, p.theta, s.s_mean, logL, top_mask, top_q,
-                       0, ss_out, vc, scal, s.redo_list, s.redo_count);
+                       0, (acc && nblk == 0) ? s.ss : nullptr, vc, scal, s.redo_list,
+                       s.redo_count, nblk > 0 ? acc_B : nullptr);
     return hipGetLastError();
   }
   int64_t blocks = (N + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_states_dsc, dim3((unsigned)blocks), dim3(256), 0, st, s.sel, s.bc, s.yy,
                      p.G, H, N, Hp, nstates, tab_act, tab_code, p.theta, s.s_mean, logL,
-                     top_mask, top_q, topk, ss_out, vc, scal, nullptr, nullptr);
+                     top_mask, top_q, topk, acc ? s.ss : nullptr, vc, scal, nullptr, nullptr,
+                     (float*)nullptr);
   return hipGetLastError();
 }
 

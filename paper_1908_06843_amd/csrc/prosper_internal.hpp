@@ -181,11 +181,15 @@ inline bool is_max_model(int m) { return m == PROSPER_MCA || m == PROSPER_MMCA; 
 // (H', gamma) = (8, 3) without top-k or annealing, else table-driven.  With
 // acc, writes pair-major <s s^T> into s.ss for the statistics kernel and adds
 // the expected value counts into vcount.
+// Training (acc, compiled walk, B's packed triangle within a statistics
+// slice): the walk writes per-workgroup B partials into s.partB instead
+// (*tree_blocks = their number) and the redo points add into acc_B.
+bool has_dsc_tree(int Hp, int gamma);
 hipError_t launch_states_dsc(int Hp, int gamma, int64_t N, int H, int64_t nstates,
                              const uint32_t* tab_act, const uint32_t* tab_code, const Prepared& p,
                              const Scratch& s, float* logL, uint32_t* top_mask, float* top_q,
                              int topk, bool acc, double* vcount, double* scal, hipStream_t st,
-                             float beta);
+                             float beta, int num_cu, int* tree_blocks, float* acc_B);
 // MCA/MMCA state walk (max / largest-magnitude superposition).
 hipError_t launch_states_max(int model, int Hp, int gamma, int64_t N, int D, int Dp, int H, int64_t nstates,
                              const uint32_t* tab_act, const float* Y, const Prepared& p,
