@@ -157,8 +157,22 @@ def error_stats(g, r):
             "logL_rel_max": float(el.max())}
 
 
+def _profile_read(lib, ctx):
+    import ctypes as C
+    cap = 16
+    names = (C.c_char_p * cap)()
+    tot = (C.c_double * cap)()
+    cnt = (C.c_int64 * cap)()
+    k = lib.prosper_profile_read(ctx.handle, cap, names, tot, cnt)
+    return {names[i].decode(): {"ms": tot[i], "launches": cnt[i]} for i in range(min(k, cap))}
+
+
 def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
-    """Warm up, then time `steps` EM iterations; returns (ms/step, profile)."""
+    """Warm up; take the per-group breakdown from a few steps with every
+    kernel group bracketed by HIP events; then time `steps` EM iterations
+    with events around the dominant group only (its launches inside the
+    timed region give the roofline).  Returns (ms/step, wall ms/step,
+    breakdown, timed dominant group, W, theta)."""
     Wd = W0.clone()
     theta = theta0.clone()
     acc = api.new_acc(wl.model, wl.D, wl.H, nvalues=len(wl.phi))
@@ -176,6 +190,13 @@ def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
     torch.cuda.synchronize()
     lib = api._lib.load()
     lib.prosper_profile(ctx.handle, 1)
+    for _ in range(min(steps, 5)):
+        step()
+    torch.cuda.synchronize()
+    prof = _profile_read(lib, ctx)
+    dom = max((k for k in prof if not k.startswith("mstep")), key=lambda k: prof[k]["ms"])
+    lib.prosper_profile(ctx.handle, 1)           # clears the counters
+    lib.prosper_profile_only(ctx.handle, dom.encode())
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -186,15 +207,10 @@ def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
     ev_ms = start.elapsed_time(stop)
-    import ctypes as C
-    cap = 16
-    names = (C.c_char_p * cap)()
-    tot = (C.c_double * cap)()
-    cnt = (C.c_int64 * cap)()
-    k = lib.prosper_profile_read(ctx.handle, cap, names, tot, cnt)
-    prof = {names[i].decode(): {"ms": tot[i], "launches": cnt[i]} for i in range(min(k, cap))}
+    timed = _profile_read(lib, ctx)
+    lib.prosper_profile_only(ctx.handle, None)
     lib.prosper_profile(ctx.handle, 0)
-    return max(ev_ms, 1e-9) / steps, wall_ms / steps, prof, Wd, theta
+    return max(ev_ms, 1e-9) / steps, wall_ms / steps, prof, {dom: timed[dom]}, Wd, theta
 
 
 def serving_bench(np, api, n_req, prec):
@@ -305,11 +321,11 @@ def side_workload(name, np, torch, api, ctx, steps, warmup, cpu_s, no_cpu):
     W0d = torch.tensor(W0, device=dev)
     theta0 = torch.tensor([pi0, s0, *pv0], dtype=torch.float64, device=dev)
     prec = "fp32" if wl.model in ("mca", "mmca") else "bf16"
-    ms, wall_ms, prof, _, _ = run_em_steps(api, torch, Yd, W0d, theta0, wl, prec, steps,
-                                           warmup, ctx)
+    ms, wall_ms, prof, timed, _, _ = run_em_steps(api, torch, Yd, W0d, theta0, wl, prec, steps,
+                                                  warmup, ctx)
     N = Y.shape[0]
-    dom = max((k for k in prof if not k.startswith("mstep")), key=lambda k: prof[k]["ms"])
-    roof = roofline(dom, prof[dom]["ms"] / prof[dom]["launches"] * 1e-3, N, wl)
+    dom = next(iter(timed))
+    roof = roofline(dom, timed[dom]["ms"] / timed[dom]["launches"] * 1e-3, N, wl)
     vals = f" V={len(wl.phi)} phi={list(wl.phi)}" if dsc else ""
     rec = {"workload": f"{wl.model.upper()} {name}: D={wl.D} H={wl.H} N={N} H'={wl.Hprime} "
                        f"gamma={wl.gamma}{vals} |K|={K}, one EM iteration",
@@ -505,9 +521,10 @@ def main():
 
     res = {}
     for prec in (["bf16"] if args.no_fp32 else ["bf16", "fp32", "bf16x1"]):
-        ms, wall_ms, prof, Wfin, thfin = run_em_steps(api, torch, Yd, W0d, theta0, wl, prec,
-                                                      args.steps, args.warmup, ctx)
-        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "profile": prof}
+        ms, wall_ms, prof, timed, Wfin, thfin = run_em_steps(api, torch, Yd, W0d, theta0, wl,
+                                                             prec, args.steps, args.warmup, ctx)
+        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "profile": prof,
+                     "timed": timed}
         print(f"# {prec}: {ms:.3f} ms/step  " +
               "  ".join(f"{k} {v['ms'] / v['launches'] * 1e3:.1f}us" for k, v in prof.items()),
               file=sys.stderr, flush=True)
@@ -532,9 +549,9 @@ def main():
 
     # roofline of the dominant kernel of the BF16 step, priced at its
     # algorithmic work against the resource that binds that work
-    prof = res["bf16"]["profile"]
-    dom = max((k for k in prof if not k.startswith("mstep")), key=lambda k: prof[k]["ms"])
-    per_launch_s = prof[dom]["ms"] / prof[dom]["launches"] * 1e-3
+    timed = res["bf16"]["timed"]
+    dom = next(iter(timed))
+    per_launch_s = timed[dom]["ms"] / timed[dom]["launches"] * 1e-3
     N = Y.shape[0]
     roof = roofline(dom, per_launch_s, N, wl)
     side = None
@@ -563,8 +580,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": {p: {"value": N * K / (r["ms_per_step"] * 1e-3),
                       "ms_per_step": r["ms_per_step"],
-                      "estep_ms": sum(v["ms"] for k, v in r["profile"].items()
-                                      if not k.startswith("mstep")) / args.steps,
+                      "estep_ms": sum(v["ms"] / v["launches"] for k, v in r["profile"].items()
+                                      if not k.startswith("mstep")),
                       "kernel_us": {k: v["ms"] / v["launches"] * 1e3
                                     for k, v in r["profile"].items()},
                       "error_vs_fp64_oracle": err.get(p)} for p, r in res.items()},

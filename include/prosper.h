@@ -196,6 +196,10 @@ const char*    prosper_last_error(const prosper_ctx* ctx);
  * entries: group name (static string), total elapsed ms and launch count.
  * Returns the number of groups (may exceed cap), or a negative status. */
 prosper_status prosper_profile(prosper_ctx* ctx, int32_t enable);
+/* Restrict the timing to the group named `group` (one of the names
+ * prosper_profile_read returns); NULL or "" times every group again.  Fewer
+ * events keep the timed work closer to the untimed one. */
+prosper_status prosper_profile_only(prosper_ctx* ctx, const char* group);
 int32_t        prosper_profile_read(prosper_ctx* ctx, int32_t cap, const char** names,
                                     double* total_ms, int64_t* launches);
 

@@ -58,7 +58,7 @@ EXPORTS = [
     "prosper_validate_args", "prosper_state_count", "prosper_state_table",
     "prosper_estep", "prosper_mstep", "prosper_mstep_et", "prosper_serve", "prosper_serve_submit",
     "prosper_serve_wait", "prosper_serve_wait_stages", "prosper_serve_stop",
-    "prosper_profile", "prosper_profile_read",
+    "prosper_profile", "prosper_profile_only", "prosper_profile_read",
     "prosper_estep_static", "prosper_dsc_state_count", "prosper_dsc_state_table",
 ]
 
@@ -116,6 +116,8 @@ def load() -> C.CDLL:
     lib.prosper_serve_stop.restype = i32
     lib.prosper_profile.argtypes = [vp, i32]
     lib.prosper_profile.restype = i32
+    lib.prosper_profile_only.argtypes = [vp, C.c_char_p]
+    lib.prosper_profile_only.restype = i32
     lib.prosper_profile_read.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(dbl),
                                          C.POINTER(i64)]
     lib.prosper_profile_read.restype = i32

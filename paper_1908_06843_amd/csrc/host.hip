@@ -62,6 +62,7 @@ struct prosper_ctx {
   std::vector<std::tuple<const char*, hipEvent_t, hipEvent_t>> ev_pending;
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<std::string> prof_order;
+  std::string prof_only;  // time only this group ("" = every group)
   // B factored ahead by an E-step (PROSPER_FLAG_FACTOR_B) on the side stream
   hipStream_t side = nullptr;
   hipEvent_t ev_b = nullptr, ev_f = nullptr;
@@ -414,7 +415,7 @@ hipEvent_t prof_event(prosper_ctx* c) {
 // Runs `launch` between two events on stream s when profiling is enabled.
 template <typename F>
 hipError_t timed(prosper_ctx* c, const char* name, hipStream_t s, F&& launch) {
-  if (!c || !c->prof) return launch();
+  if (!c || !c->prof || (!c->prof_only.empty() && c->prof_only != name)) return launch();
   hipEvent_t a = prof_event(c), b = prof_event(c);
   hipEventRecord(a, s);
   hipError_t e = launch();
@@ -640,6 +641,12 @@ prosper_status prosper_profile(prosper_ctx* c, int32_t enable) {
   c->prof_tab.clear();
   c->prof_order.clear();
   c->prof = enable != 0;
+  return PROSPER_OK;
+}
+
+prosper_status prosper_profile_only(prosper_ctx* c, const char* group) {
+  if (!c) return fail(nullptr, PROSPER_EINVAL, "ctx is NULL");
+  c->prof_only = group ? group : "";
   return PROSPER_OK;
 }
 
