@@ -639,15 +639,16 @@ static hipError_t launch_project_select_body(int model, int prec, const float* Y
   // exact in FP32; the head*head sum sees D + 1 roundings, the cross sum
   // (terms below 2^-7 of the head*head ones) 2 D + 1, and one rounding adds
   // the two.  3% slack.
-  // BF16X1 (one head*head product): each operand's head is within 2^-9 of
-  // it, so a product is within 2^-8 + 2^-18 of y_d P_hd (exact in FP32), plus
-  // the D + 1 roundings of the accumulation.
+  // BF16X1 (one head*head product): BF16 keeps 8 significant bits, so each
+  // operand's head is within 2^-8 of it and a product of heads (exact in
+  // FP32) is within 2^-7 + 2^-16 of y_d P_hd, plus the D + 1 roundings of the
+  // accumulation.
   const double u = 1.0 / 16777216.0;  // 2^-24
   const float kappa =
       (prec == PROSPER_FP32)
           ? (float)(1.01 * (D + 2) * u)
           : (prec == PROSPER_BF16X1)
-                ? (float)(1.03 * (1.0 / 256.0 + 1.0 / 262144.0 + (D + 2) * u))
+                ? (float)(1.03 * (1.0 / 128.0 + 1.0 / 65536.0 + (D + 2) * u))
                 : (float)(1.03 * (3.0 / 65536.0 + (D + 2) * u + (2.0 * D + 1) * u / 128.0 + u));
   const int tm = choose_tm(Dp, H, prec);
   const size_t lds = project_lds_bytes(Dp, H, prec, tm);
