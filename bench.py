@@ -5,8 +5,9 @@ Workload: BSC, D = H = 256, N = 200000 points, H' = 12, gamma = 4
 (|K| = 794 states per point), synthetic data from the generative model
 (Gaussian unit-norm dictionary, pi = 5/256, sigma = 0.5).
 
-One step = one EM iteration on the device: clear the accumulators, the
-truncated E-step with statistic accumulation (parameter prep, projection +
+One step = one EM iteration on the device: the truncated E-step with
+statistics written into cleared accumulators (parameter prep with the
+clearing, projection +
 preselection, state walk, A accumulation; the FP64 Cholesky factor of B is
 formed on a second stream meanwhile) and the FP64 M-step solve, with W, pi
 and sigma staying in device memory.  The metric is joint evaluations per
@@ -179,10 +180,10 @@ def run_em_steps(api, torch, Yd, W0, theta0, wl, prec, steps, warmup, ctx):
     factor_b = wl.model in ("bsc", "tsc", "dsc")
     phi = wl.phi if wl.model == "dsc" else None
 
-    def step():
-        api.zero_acc(acc)
+    def step():   # the E-step clears the accumulators (zero_acc)
         api.estep(Yd, Wd, Hprime=wl.Hprime, gamma=wl.gamma, model=wl.model, precision=prec,
-                  theta=theta, acc=acc, want=(), ctx=ctx, factor_b=factor_b, phi=phi)
+                  theta=theta, acc=acc, want=(), ctx=ctx, factor_b=factor_b, phi=phi,
+                  zero_acc=True)
         api.mstep(acc, Wd, model=wl.model, W_new=Wd, theta_new=theta, ctx=ctx)
 
     for _ in range(warmup):

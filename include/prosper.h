@@ -93,6 +93,11 @@ typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1, PROSPER_BF16X1 = 2 } prosper_
  * or any prosper_mstep, on the context discards it; the caller must not
  * modify acc->B in between. */
 #define PROSPER_FLAG_FACTOR_B      1u
+/* PROSPER_FLAG_ZERO_ACC (accumulate = 1 only): the call overwrites acc (A, B,
+ * scal and, for DSC, vcount) with this call's statistics instead of adding
+ * into them; the clearing rides on the parameter-preparation kernels, so an
+ * EM loop needs no separate fill of the accumulators. */
+#define PROSPER_FLAG_ZERO_ACC      2u
 
 /* Limits of this build */
 #define PROSPER_MAX_HPRIME   32
@@ -118,7 +123,8 @@ typedef struct {
     int32_t topk;           /* 0..PROSPER_MAX_TOPK most probable states per point;
                                topk <= |K| */
     int32_t accumulate;     /* 1: add the M-step sufficient statistics into acc */
-    uint32_t flags;         /* PROSPER_FLAG_NONE or PROSPER_FLAG_FACTOR_B */
+    uint32_t flags;         /* PROSPER_FLAG_NONE, or PROSPER_FLAG_FACTOR_B and/or
+                               PROSPER_FLAG_ZERO_ACC */
     float   beta;           /* posterior temperature of deterministic annealing (the
                                schedule object of the paper's user-interface section):
                                q_n(s) proportional to p(y_n, s | Theta)^beta on K_n, in

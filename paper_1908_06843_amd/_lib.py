@@ -30,6 +30,7 @@ class ProsperError(RuntimeError):
 
 
 FLAG_FACTOR_B = 1  # PROSPER_FLAG_FACTOR_B
+FLAG_ZERO_ACC = 2  # PROSPER_FLAG_ZERO_ACC
 
 
 class Args(C.Structure):

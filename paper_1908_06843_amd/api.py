@@ -113,7 +113,7 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
           ctx: Optional[Context] = None, stream: Optional[torch.cuda.Stream] = None,
           factor_b: bool = False, static: bool = False,
           beta: float = 1.0, phi: Optional[Sequence[float]] = None,
-          pv: Optional[Sequence[float]] = None) -> Dict[str, torch.Tensor]:
+          pv: Optional[Sequence[float]] = None, zero_acc: bool = False) -> Dict[str, torch.Tensor]:
     """Truncated E-step over the rows of Y (N x D) for dictionary W (D x H).
 
     Returns the requested per-point outputs: sel (N x H' int32), s_mean
@@ -129,6 +129,8 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
     intermediates live in the library's fixed device array); no context.
     `beta` is the posterior temperature of deterministic annealing (q
     proportional to p(y, s)^beta; logL untempered).
+    `zero_acc` (with `acc`): overwrite the accumulators instead of adding into
+    them (PROSPER_FLAG_ZERO_ACC; no separate clearing needed).
     DSC (model="dsc"): `phi` is the value set (phi[0] = 0) and `pv` its prior
     (ignored when `theta` = (pi, sigma, pv_0 .. pv_{V-1}) is given); top_mask
     is N x topk x 4 (active mask, three bit planes of the value codes).
@@ -176,9 +178,9 @@ def estep(Y: torch.Tensor, W: torch.Tensor, pi: float = 0.5, sigma: float = 1.0,
         accs = _acc_struct(acc)
     if model == "dsc" and phi is None:
         raise ValueError("DSC needs the value set phi")
+    flags = (_lib.FLAG_FACTOR_B if factor_b else 0) | (_lib.FLAG_ZERO_ACC if zero_acc else 0)
     args = _lib.make_args(model, precision, N, D, H, Hprime, gamma, pi, sigma,
-                          _ptr(theta), topk, 1 if acc is not None else 0,
-                          _lib.FLAG_FACTOR_B if factor_b else 0, beta,
+                          _ptr(theta), topk, 1 if acc is not None else 0, flags, beta,
                           phi if model == "dsc" else None, pv if model == "dsc" else None)
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lib = _lib.load()

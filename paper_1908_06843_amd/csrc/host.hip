@@ -309,8 +309,12 @@ prosper_status validate(const prosper_args* a, std::string* msg, int64_t* nstate
     *msg = "beta (posterior temperature) outside (0, 1]";
     return PROSPER_EINVAL;
   }
-  if ((a->flags & ~PROSPER_FLAG_FACTOR_B) != 0u) {
+  if ((a->flags & ~(PROSPER_FLAG_FACTOR_B | PROSPER_FLAG_ZERO_ACC)) != 0u) {
     *msg = "unknown flag bits";
+    return PROSPER_EINVAL;
+  }
+  if ((a->flags & PROSPER_FLAG_ZERO_ACC) && !a->accumulate) {
+    *msg = "PROSPER_FLAG_ZERO_ACC needs accumulate = 1";
     return PROSPER_EINVAL;
   }
   if ((a->flags & PROSPER_FLAG_FACTOR_B) && (!a->accumulate || is_max_model(a->model))) {
@@ -585,11 +589,22 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
   float* Bacc = a->accumulate ? acc->B : nullptr;
   double* scal = a->accumulate ? acc->scal : nullptr;
   int tree_blocks = 0;
+  // PROSPER_FLAG_ZERO_ACC: the preparation kernels clear the accumulators
+  const bool zero = a->accumulate && (a->flags & PROSPER_FLAG_ZERO_ACC);
+  AccZero z;
+  if (zero) {
+    z.A = Aacc;
+    z.B = Bacc;
+    z.B_dh = is_max_model(model);
+    z.scal = scal;
+    z.vcount = model == PROSPER_DSC ? acc->vcount : nullptr;
+    z.nv = model == PROSPER_DSC ? a->nvalues : 0;
+  }
   hipError_t e = timed(c, "prep", s, [&] {
     hipError_t e2 = launch_theta_full(model, D, H, a->pi, a->sigma, a->theta_dev, p,
                                       sc.redo_count, s, sc.defer_count, args_beta(a),
-                                      dsc_params(a));
-    return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp, p, s) : e2;
+                                      dsc_params(a), z);
+    return e2 == hipSuccess ? launch_prep(model, prec, W, D, H, Dp, p, s, z) : e2;
   });
   if (e == hipSuccess)
     e = timed(c, "project_select", s, [&] {

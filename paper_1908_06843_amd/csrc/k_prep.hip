@@ -19,8 +19,13 @@ namespace prosper {
 __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
                         const double* __restrict__ theta_dev, Theta* __restrict__ th,
                         float* __restrict__ pnorm, int32_t* __restrict__ redo_count,
-                        int32_t* __restrict__ defer_count, float beta, DscParams dsc) {
+                        int32_t* __restrict__ defer_count, float beta, DscParams dsc,
+                        double* __restrict__ zscal, double* __restrict__ zvc, int nvc) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (zscal)
+    for (int i = 0; i < 5; ++i) zscal[i] = 0.0;
+  if (zvc)
+    for (int v = 0; v < nvc; ++v) zvc[v] = 0.0;
   double pi = theta_dev ? theta_dev[0] : pi_h;
   double sigma = theta_dev ? theta_dev[1] : sigma_h;
   const double LOG2E = 1.4426950408889634;
@@ -70,10 +75,13 @@ __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
 
 // Pt32[h][d] = P[d][h] (zero for d >= D), P = W or max(W, 0) (MCA, H > 1);
 // optional BF16 head/tail split.  32 x 32 tiles through LDS.
+// zA, zB (optional): D x H accumulators cleared on the way (same index map as W).
 __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, int D, int H,
                                                    int Dp, int relu, float* __restrict__ Pt32,
                                                    bf16* __restrict__ Pt_hi,
-                                                   bf16* __restrict__ Pt_lo) {
+                                                   bf16* __restrict__ Pt_lo,
+                                                   float* __restrict__ zA,
+                                                   float* __restrict__ zB) {
   __shared__ float tile[32][33];
   const int d0 = blockIdx.x * 32, h0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -83,6 +91,8 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, 
     if (d < D && h < H) {
       v = W[(int64_t)d * H + h];
       if (relu) v = fmaxf(v, 0.0f);
+      if (zA) zA[(int64_t)d * H + h] = 0.0f;
+      if (zB) zB[(int64_t)d * H + h] = 0.0f;
     }
     tile[r][tx] = v;
   }
@@ -103,8 +113,9 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, 
 }
 
 // G[i][j] = sum_d W[d][i] W[d][j], FP64 accumulation, 16 x 16 output tiles.
+// zB (optional): the H x H accumulator cleared on the way.
 __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D, int H,
-                                              float* __restrict__ G) {
+                                              float* __restrict__ G, float* __restrict__ zB) {
   __shared__ double a[16][17], b[16][17];
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -118,7 +129,10 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D
     for (int k = 0; k < 16; ++k) acc = fma(a[k][ty], b[k][tx], acc);
     __syncthreads();
   }
-  if (i0 + ty < H && j0 + tx < H) G[(int64_t)(i0 + ty) * H + j0 + tx] = (float)acc;
+  if (i0 + ty < H && j0 + tx < H) {
+    G[(int64_t)(i0 + ty) * H + j0 + tx] = (float)acc;
+    if (zB) zB[(int64_t)(i0 + ty) * H + j0 + tx] = 0.0f;
+  }
 }
 
 // hn[h] = 1/2 ||P_h||^2 in FP64 split into an FP32 head and tail; running
@@ -155,15 +169,15 @@ __global__ __launch_bounds__(256) void k_rowmax(const float* __restrict__ W, int
 }
 
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
-                       const Prepared& p, hipStream_t st) {
+                       const Prepared& p, hipStream_t st, const AccZero& z) {
   const int relu = (model == PROSPER_MCA && H > 1) ? 1 : 0;
   dim3 gt((Dp + 31) / 32, (H + 31) / 32);
   hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, st, W, D, H, Dp, relu, p.Pt32,
                      prec != PROSPER_FP32 ? p.Pt_hi : nullptr,
-                     prec != PROSPER_FP32 ? p.Pt_lo : nullptr);
+                     prec != PROSPER_FP32 ? p.Pt_lo : nullptr, z.A, z.B_dh ? z.B : nullptr);
   if (!is_max_model(model)) {
     dim3 gg((H + 15) / 16, (H + 15) / 16);
-    hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G);
+    hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G, z.B_dh ? nullptr : z.B);
   }
   hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi, p.hn_lo,
                      p.pnorm);
@@ -177,9 +191,10 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
                              hipStream_t st, int32_t* defer_count, float beta,
-                             const DscParams& dsc) {
+                             const DscParams& dsc, const AccZero& z) {
   hipLaunchKernelGGL(k_theta, dim3(1), dim3(64), 0, st, model, D, H, pi, sigma, theta_dev,
-                     p.theta, p.pnorm, redo_count, defer_count, beta, dsc);
+                     p.theta, p.pnorm, redo_count, defer_count, beta, dsc, z.scal, z.vcount,
+                     z.nv);
   return hipGetLastError();
 }
 

@@ -148,12 +148,22 @@ size_t prep_bytes(int Dp, int H, int prec);
 Prepared carve_prep(void* base, int Dp, int H, int prec);
 
 // Launchers (each returns the first HIP error it sees).
+// Accumulators the preparation kernels clear (PROSPER_FLAG_ZERO_ACC): A is
+// D x H; B is H x H, or D x H for the max models (B_dh).
+struct AccZero {
+  float* A = nullptr;
+  float* B = nullptr;
+  bool B_dh = false;
+  double* scal = nullptr;
+  double* vcount = nullptr;
+  int nv = 0;
+};
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
                              hipStream_t st, int32_t* defer_count = nullptr, float beta = 1.0f,
-                             const DscParams& dsc = DscParams());
+                             const DscParams& dsc = DscParams(), const AccZero& z = AccZero());
 hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp,
-                       const Prepared& p, hipStream_t st);
+                       const Prepared& p, hipStream_t st, const AccZero& z = AccZero());
 // Entries of the projection's deferral list for N points: enough for a
 // quarter of them (0 where every point takes the exact path anyway).
 int project_defer_capacity(int64_t N, int H, int Hp, int prec = PROSPER_BF16);

@@ -285,11 +285,10 @@ class EM:
         factor_b = m.kind in ("bsc", "tsc", "dsc")
         for it in range(self.anneal.iterations):
             beta = self.anneal.beta(it)
-            api.zero_acc(acc)
             want = ("logL", "k_mean", "res") if self.selected_points else ()
             pts = api.estep(Y, W, Hprime=m.Hprime, gamma=m.gamma, model=m.kind,
                             precision=m.precision, theta=theta, acc=acc, want=want, ctx=ctx,
-                            factor_b=factor_b, beta=beta, phi=m._phi())
+                            factor_b=factor_b, beta=beta, phi=m._phi(), zero_acc=True)
             if self.selected_points:
                 api.mstep_et(acc, W, pts, gamma=m.gamma, model=m.kind, theta=theta,
                              W_new=W_next, theta_new=theta, ctx=ctx)

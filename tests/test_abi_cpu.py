@@ -95,7 +95,7 @@ def test_validate_accepts_good_args():
                                  dict(gamma=-1), dict(gamma=5), dict(pi=0.0), dict(pi=1.0),
                                  dict(pi=float("nan")), dict(sigma=0.0), dict(sigma=-1.0),
                                  dict(sigma=float("inf")), dict(topk=9), dict(topk=-1),
-                                 dict(accumulate=2), dict(flags=2), dict(flags=1),
+                                 dict(accumulate=2), dict(flags=8), dict(flags=1),
                                  dict(Hprime=2, gamma=1, topk=4)])
 def test_validate_rejects_each_bad_field(bad):
     a = good_args(**bad)
@@ -217,3 +217,11 @@ def test_dsc_validate():
         a = dsc_args(**bad)
         want = 0 if "gamma" in bad else -1
         assert _lib.validate(a) == want, bad
+
+
+def test_zero_acc_flag_needs_accumulate():
+    assert _lib.validate(good_args(accumulate=1, flags=_lib.FLAG_ZERO_ACC)) == 0
+    assert _lib.validate(good_args(accumulate=1,
+                                   flags=_lib.FLAG_ZERO_ACC | _lib.FLAG_FACTOR_B)) == 0
+    assert _lib.validate(good_args(accumulate=0, flags=_lib.FLAG_ZERO_ACC)) == -1
+    assert _lib.validate(good_args(accumulate=1, flags=4)) == -1

@@ -195,3 +195,29 @@ def test_mstep_solve_many_panels(H, D, inactive):
         np.testing.assert_array_equal(Wn[:, h], W_old[:, h])
     assert th[0] == pytest.approx(scal[0] / (N * H), rel=1e-12)
     assert th[1] == pytest.approx(np.sqrt(s2), rel=1e-6)
+
+
+@pytest.mark.parametrize("model,name,Hp,gamma", [("bsc", "bsc256", 12, 4), ("mca", "mca", 10, 3),
+                                                 ("tsc", "tsc", 8, 3)])
+def test_zero_acc_flag_overwrites_the_accumulators(model, name, Hp, gamma):
+    """PROSPER_FLAG_ZERO_ACC on accumulators holding garbage gives the same
+    sums as an accumulating call on cleared ones (up to the order of the
+    atomic additions, which is not fixed between runs)."""
+    import torch
+    from paper_1908_06843_amd import api
+    from tests._common import problem
+    Y, W, pi, sigma, wl = problem(name, 3000, "init")
+    dev = torch.device("cuda", 0)
+    Yd, Wd = torch.tensor(Y, device=dev), torch.tensor(W, device=dev)
+    a = api.new_acc(model, W.shape[0], W.shape[1])
+    b = api.new_acc(model, W.shape[0], W.shape[1])
+    for t in b.values():
+        t.fill_(123.0)
+    api.estep(Yd, Wd, pi, sigma, Hprime=Hp, gamma=gamma, model=model, acc=a, want=())
+    api.estep(Yd, Wd, pi, sigma, Hprime=Hp, gamma=gamma, model=model, acc=b, want=(),
+              zero_acc=True)
+    torch.cuda.synchronize()
+    for k in a:
+        x, y = a[k].double(), b[k].double()
+        err = float((x - y).abs().max() / x.abs().max().clamp_min(1e-30))
+        assert err < 1e-6, (k, err)
