@@ -85,9 +85,9 @@ typedef enum { PROSPER_FP32 = 0, PROSPER_BF16 = 1, PROSPER_BF16X1 = 2 } prosper_
 /* PROSPER_FLAG_FACTOR_B (BSC/TSC, accumulate = 1 only; EINVAL otherwise):
  * this call completes the accumulation of acc for the next M-step.  After
  * adding its own <s s^T> into acc->B, the library factors B (the Cholesky
- * factor prosper_mstep needs, see there) in the context's workspace on a
- * second stream, overlapped with the A statistics of the same call; the call
- * still completes on `stream` only when the factor is done.  A following
+ * factor prosper_mstep needs, see there) in the context's workspace on
+ * `stream`, while the A statistics of the same call run on a second stream of
+ * the context; the call completes on `stream` once both are done.  A following
  * prosper_mstep on the same context with the same acc->B pointer, D, H and
  * model reuses that factor and only solves.  Any later accumulating E-step,
  * or any prosper_mstep, on the context discards it; the caller must not

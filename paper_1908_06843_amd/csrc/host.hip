@@ -465,7 +465,7 @@ hipError_t launch_estep_core(int model, int prec, const float* Y, int64_t N, int
   e = launch_states_lin(model, Hp, gamma, N, H, ns, tab_act, tab_sgn, p, sc, logL, top_mask,
                         top_q, topk, A != nullptr, B, scal, num_cu, &tree_blocks, s);
   if (e == hipSuccess && A)
-    e = launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, A, B, s, StatsHook(), 0);
+    e = launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, A, B, s, STATS_ALL, 0);
   return e;
 }
 }  // namespace prosper
@@ -576,7 +576,7 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
                          const prosper_point_out* out, const prosper_acc* acc, hipStream_t s,
                          const Prepared& p, const Scratch& sc, const uint32_t* tab_act,
                          const uint32_t* tab_sgn, int64_t ns, int num_cu,
-                         const StatsHook& after_B, int reserve_cu) {
+                         const StatsHook& after_B, int reserve_cu, hipStream_t a_stream) {
   const int model = a->model, prec = a->precision;
   const int64_t N = a->N;
   const int D = a->D, H = a->H, Hp = a->Hprime;
@@ -626,11 +626,28 @@ hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, 
                                &tree_blocks, s, args_beta(a), out ? out->k_mean : nullptr,
                                out ? out->res : nullptr);
     });
-  if (e == hipSuccess && Aacc && !is_max_model(model))
-    e = timed(c, "stats", s, [&] {
-      return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s, after_B,
-                          reserve_cu);
-    });
+  if (e == hipSuccess && Aacc && !is_max_model(model)) {
+    if (!after_B) {
+      e = timed(c, "stats", s, [&] {
+        return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s, STATS_ALL,
+                            reserve_cu);
+      });
+    } else {
+      // B first; then the hook (queues work on s that needs only B); then A,
+      // on a_stream when given
+      hipStream_t as = a_stream ? a_stream : s;
+      e = timed(c, "stats", s, [&] {
+        return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, s, STATS_B,
+                            reserve_cu);
+      });
+      if (e == hipSuccess) e = after_B(s);
+      if (e == hipSuccess)
+        e = timed(c, "stats_A", as, [&] {
+          return launch_stats(Y, N, D, H, Hp, sc, sc.plan, tree_blocks, Aacc, Bacc, as, STATS_A,
+                              reserve_cu);
+        });
+    }
+  }
   return e;
 }
 
@@ -675,7 +692,7 @@ int32_t prosper_profile_read(prosper_ctx* c, int32_t cap, const char** names, do
       // the names are string literals of this library
       static const char* known[] = {"prep",         "project_select", "states_lin",
                                     "states_max",   "states_dsc",     "stats",
-                                    "mstep_factor", "mstep"};
+                                    "stats_A",      "mstep_factor",   "mstep"};
       const char* nm = "";
       for (const char* k : known)
         if (n == k) nm = k;
@@ -830,18 +847,22 @@ prosper_status prosper_estep(prosper_ctx* c, const prosper_args* a, const float*
     e = ensure(c->mwork, mstep_workspace_bytes(model, D, H));
     if (e != hipSuccess) return fail(c, PROSPER_ENOMEM, "M-step workspace allocation failed");
   }
-  // after B is complete: fork its factorisation onto the side stream
+  // after B is complete: the A statistics move to the side stream and B's
+  // factorisation follows on the caller's stream (it ends after A, so the
+  // join below finds A done and the M-step's solve follows the factor on the
+  // same stream)
   auto after_B = [&](hipStream_t st2) -> hipError_t {
     hipError_t e2 = hipEventRecord(c->ev_b, st2);
     if (e2 == hipSuccess) e2 = hipStreamWaitEvent(c->side, c->ev_b, 0);
     if (e2 == hipSuccess)
-      e2 = timed(c, "mstep_factor", c->side,
-                 [&] { return launch_mstep_factor(model, D, H, acc->B, c->mwork.p, c->side); });
-    if (e2 == hipSuccess) e2 = hipEventRecord(c->ev_f, c->side);
+      e2 = timed(c, "mstep_factor", st2,
+                 [&] { return launch_mstep_factor(model, D, H, acc->B, c->mwork.p, st2); });
     return e2;
   };
   e = enqueue_estep(c, a, Y, W, out, acc, s, p, sc, tab->act, tab->sgn, ns, c->num_cu,
-                    factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 32 : 0);
+                    factor_b ? StatsHook(after_B) : StatsHook(), factor_b ? 32 : 0,
+                    factor_b ? c->side : nullptr);
+  if (e == hipSuccess && factor_b) e = hipEventRecord(c->ev_f, c->side);
   if (e == hipSuccess && factor_b) e = hipStreamWaitEvent(s, c->ev_f, 0);
   if (e != hipSuccess) return hip_fail(c, e, "E-step launch");
   if (factor_b) {

@@ -447,7 +447,7 @@ int stats_bslice_count(int H) { return bslice_count(H); }
 // that work forked by the hook finds room.
 hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
                         const StatsPlan& pl, int tree_blocks, float* A, float* B,
-                        hipStream_t st, const StatsHook& after_B, int reserve_cu) {
+                        hipStream_t st, int part, int reserve_cu) {
   if (N <= 0) return hipSuccess;
   const size_t ldsA = (size_t)H * (pl.DS + 1) * 4;
   const bool mfmaA = stats_a_mfma_ok(D, H);
@@ -476,9 +476,10 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
     return hipGetLastError();
   };
   if (mfmaA) {
-    hipError_t e = reduce_B_and_A(false);
-    if (e == hipSuccess && after_B) e = after_B(st);
-    if (e != hipSuccess) return e;
+    if (part != STATS_A) {
+      hipError_t e = reduce_B_and_A(false);
+      if (e != hipSuccess || part == STATS_B) return e;
+    }
     const int64_t ntiles = (N + AT_PTS - 1) / AT_PTS;
     int cap = pl.mfma_wgs - reserve_cu;
     if (cap < 1) cap = 1;
@@ -498,6 +499,9 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
                        D, H, nwg, s.partA, A);
     return hipGetLastError();
   }
+  // without the MFMA form A is formed first and reduced with B: all of it in
+  // the B part, nothing left for the A part
+  if (part == STATS_A) return hipSuccess;
   const int which = Hp <= 16 ? 0 : 1;
   const void* kern = which == 0 ? reinterpret_cast<const void*>(k_stats_A<16>)
                                 : reinterpret_cast<const void*>(k_stats_A<32>);
@@ -512,9 +516,7 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
   else
     hipLaunchKernelGGL(k_stats_A<32>, g, dim3(256), ldsA, st, Y, N, D, H, Hp, s.sel, s.s_mean,
                        pl.DS, pl.nA, pl.ppg, s.partA);
-  hipError_t e = reduce_B_and_A(true);
-  if (e == hipSuccess && after_B) e = after_B(st);
-  return e;
+  return reduce_B_and_A(true);
 }
 
 }  // namespace prosper

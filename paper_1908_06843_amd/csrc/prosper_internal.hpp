@@ -210,11 +210,16 @@ int stats_bslice_floats();
 bool stats_a_mfma_ok(int D, int H);
 int stats_bslice_count(int H);
 // Called on the E-step stream once B holds every contribution of the call
-// (before the A statistics are formed), to fork work that needs only B.
+// (before the A statistics are formed), to queue work that needs only B.
 typedef std::function<hipError_t(hipStream_t)> StatsHook;
+// The statistics in two parts: STATS_B completes B (and, where A is not
+// formed on MFMA, A too); STATS_A forms A (MFMA form; nothing otherwise).
+// STATS_ALL is both on one stream.  The A part may run on another stream
+// once the B part has been issued (it reads only the walk's outputs and Y).
+enum { STATS_ALL = 0, STATS_B = 1, STATS_A = 2 };
 hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const Scratch& s,
                         const StatsPlan& pl, int tree_blocks, float* A, float* B, hipStream_t st,
-                        const StatsHook& after_B, int reserve_cu);
+                        int part, int reserve_cu);
 // M-step.
 size_t mstep_workspace_bytes(int model, int D, int H);
 hipError_t launch_mstep(int model, int D, int H, const float* A, const float* B,
@@ -272,11 +277,15 @@ Scratch carve_estep(void* base, const EstepLayout& L, const prosper_args* a,
 // E-step on stream s.  c may be NULL (no profiling).  after_B runs once B is
 // complete; reserve_cu CUs are left free for work it forks.
 // num_cu: the CU count the statistics partials of the layout were planned for.
+// With after_B and a_stream, the A statistics run on a_stream after the hook
+// (which the caller uses to queue B's factorisation on s); the caller joins
+// a_stream back into s.
 hipError_t enqueue_estep(prosper_ctx* c, const prosper_args* a, const float* Y, const float* W,
                          const prosper_point_out* out, const prosper_acc* acc, hipStream_t s,
                          const Prepared& p, const Scratch& sc, const uint32_t* tab_act,
                          const uint32_t* tab_sgn, int64_t ns, int num_cu,
-                         const StatsHook& after_B, int reserve_cu);
+                         const StatsHook& after_B, int reserve_cu,
+                         hipStream_t a_stream = nullptr);
 // Records the text of a failure of a context-less call (prosper_last_error(NULL)).
 prosper_status set_error(prosper_status st, const std::string& msg);
 
