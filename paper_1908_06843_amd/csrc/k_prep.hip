@@ -112,29 +112,37 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, 
   }
 }
 
-// G[i][j] = sum_d W[d][i] W[d][j], FP64 accumulation: 32 x 32 output tiles,
-// each thread a 2 x 2 block (rows ty, ty + 16, columns tx, tx + 16), depth in
-// chunks of 32 rows of W staged through LDS with coalesced 128-byte loads.
-// zB (optional): the H x H accumulator cleared on the way.
+// G[i][j] = sum_d W[d][i] W[d][j], FP64 accumulation, one 16 x 16 output tile
+// per workgroup.  Depth goes in chunks of 256 rows of W: both 16-column slabs
+// of a chunk are staged in LDS by one load phase, the four waves take 64 rows
+// each (every lane a 2 x 2 block of the tile), and the four partial tiles are
+// summed in wave order at the end.  zB (optional): the H x H accumulator
+// cleared on the way.
 __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D, int H,
                                               float* __restrict__ G, float* __restrict__ zB) {
-  __shared__ double a[32][33], b[32][33];  // a[k][c] = W[d0 + k][i0 + c], b likewise at j0
-  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  constexpr int KC = 256;
+  __shared__ float a[KC][16], b[KC][16];  // a[k][c] = W[d0 + k][i0 + c], b likewise at j0
+  __shared__ double part[4][16][16];
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = (lane >> 3) * 2, c = (lane & 7) * 2;
   double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
-  for (int d0 = 0; d0 < D; d0 += 32) {
+  for (int d0 = 0; d0 < D; d0 += KC) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < KC * 16 / 256; ++u) {
       const int e = threadIdx.x + 256 * u;
-      const int k = e >> 5, c = e & 31;
+      const int k = e >> 4, q = e & 15;
       const int d = d0 + k;
-      a[k][c] = (d < D && i0 + c < H) ? (double)W[(int64_t)d * H + i0 + c] : 0.0;
-      b[k][c] = (d < D && j0 + c < H) ? (double)W[(int64_t)d * H + j0 + c] : 0.0;
+      a[k][q] = (d < D && i0 + q < H) ? W[(int64_t)d * H + i0 + q] : 0.0f;
+      b[k][q] = (d < D && j0 + q < H) ? W[(int64_t)d * H + j0 + q] : 0.0f;
     }
     __syncthreads();
+    const int k0 = wave * (KC / 4);
 #pragma unroll 8
-    for (int k = 0; k < 32; ++k) {
-      const double a0 = a[k][ty], a1 = a[k][ty + 16], b0 = b[k][tx], b1 = b[k][tx + 16];
+    for (int k = k0; k < k0 + KC / 4; ++k) {
+      const float2 av = *reinterpret_cast<const float2*>(&a[k][r]);
+      const float2 bv = *reinterpret_cast<const float2*>(&b[k][c]);
+      const double a0 = av.x, a1 = av.y, b0 = bv.x, b1 = bv.y;
       acc00 = fma(a0, b0, acc00);
       acc01 = fma(a0, b1, acc01);
       acc10 = fma(a1, b0, acc10);
@@ -142,17 +150,18 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D
     }
     __syncthreads();
   }
-  const double accs[2][2] = {{acc00, acc01}, {acc10, acc11}};
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = i0 + ty + 16 * r, j = j0 + tx + 16 * q;
-      if (i < H && j < H) {
-        G[(int64_t)i * H + j] = (float)accs[r][q];
-        if (zB) zB[(int64_t)i * H + j] = 0.0f;
-      }
-    }
+  part[wave][r][c] = acc00;
+  part[wave][r][c + 1] = acc01;
+  part[wave][r + 1][c] = acc10;
+  part[wave][r + 1][c + 1] = acc11;
+  __syncthreads();
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  const int i = i0 + ti, j = j0 + tj;
+  if (i < H && j < H) {
+    const double g = ((part[0][ti][tj] + part[1][ti][tj]) + part[2][ti][tj]) + part[3][ti][tj];
+    G[(int64_t)i * H + j] = (float)g;
+    if (zB) zB[(int64_t)i * H + j] = 0.0f;
+  }
 }
 
 // hn[h] = 1/2 ||P_h||^2 in FP64 split into an FP32 head and tail; running
@@ -196,7 +205,7 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
                      prec != PROSPER_FP32 ? p.Pt_hi : nullptr,
                      prec != PROSPER_FP32 ? p.Pt_lo : nullptr, z.A, z.B_dh ? z.B : nullptr);
   if (!is_max_model(model)) {
-    dim3 gg((H + 31) / 32, (H + 31) / 32);
+    dim3 gg((H + 15) / 16, (H + 15) / 16);
     hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G, z.B_dh ? nullptr : z.B);
   }
   hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi, p.hn_lo,

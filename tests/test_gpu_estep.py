@@ -51,6 +51,22 @@ def test_generic_kernel_shapes():
         assert_parity(g, r, "fp32", f"generic H'={Hp} g={gamma}")
 
 
+@pytest.mark.parametrize("model", ["bsc", "tsc"])
+def test_deep_ragged_dictionary(model):
+    """D = 300 (two depth chunks of the W^T W kernel, the second partial) and
+    H = 37 (a partial 16 x 16 tile) with the generic walk."""
+    g = synth.rng(31)
+    D, H, N, pi, sigma = 300, 37, 401, 0.08, 0.6
+    W = synth.unit_norm_gaussian_dictionary(g, D, H) * 2.0
+    S = (synth.sample_binary if model == "bsc" else synth.sample_ternary)(g, N, H, pi)
+    Y = np.ascontiguousarray(synth.linear_observations(g, W, S, sigma), dtype=np.float32)
+    W = np.ascontiguousarray(W, dtype=np.float32)
+    for prec in ("fp32", "bf16"):
+        gout = gpu_estep(model, prec, Y, W, pi, sigma, 7, 3)
+        r = O.estep(model, Y, W, pi, sigma, 7, 3)
+        assert_parity(gout, r, prec, f"{model} D={D} H={H} {prec}")
+
+
 def test_gamma_zero_and_one():
     Y, W, pi, sigma, wl = problem("bsc256", 200, "gt")
     for Hp, gamma in [(4, 0), (6, 1)]:
