@@ -19,16 +19,18 @@
 //                panels.  Every workgroup factors the 64 x 64 diagonal block
 //                in one wave's registers (lane i holds row i), then solves
 //                64 of the rows below against it by forward substitution,
-//                one thread per row.  L is written to the lower triangle and
-//                mirrored into the upper one, so that both substitutions of
-//                the solve read coalesced rows;
-//   k_ms_invdiag: after the last panel, the inverses of all diagonal blocks
-//                at once (row-major and transposed), for the solve;
+//                one thread per row, while another wave inverts the block.
+//                The off-diagonal blocks of L are written to the lower
+//                triangle and mirrored into the upper one, so that both
+//                substitutions of the solve read coalesced rows; the
+//                diagonal blocks are kept as their inverses (row-major and
+//                transposed);
 //   k_ms_syrk  : trailing update T -= P P^T on 32 x 32 tiles;
-//   k_ms_solve : one wave per pixel d: block forward and backward
-//                substitution of x, each block step a few matrix-vector
-//                products (the diagonal ones with the stored inverses);
-//                then W_new row d and its share of tr(W_new^T A).
+//   k_ms_solve : four pixels per workgroup: block forward and backward
+//                substitution, each block step a few matrix-vector products
+//                (the diagonal ones with the stored inverses) whose matrix
+//                reads serve the four pixels; then W_new row d and its share
+//                of tr(W_new^T A).
 // MCA: W_new = A / B elementwise where B > 0 (hard-max responsibilities),
 // pi as above, sigma^2 = sum <||y - f(s)||^2> / (N D).
 #include "dev_common.hpp"
@@ -72,30 +74,28 @@ static MstepWork carve_mstep(void* work, int D, int H) {
   return w;
 }
 
-__global__ __launch_bounds__(1024) void k_ms_begin(int H, const float* __restrict__ Bup,
-                                                   MstepHdr* __restrict__ hdr) {
-  __shared__ double red[16];
+// M = symmetrised active block of B (+ jitter), identity on inactive latents.
+// Every workgroup sums the active diagonal itself (H loads, in the same order
+// everywhere, so all find the same jitter); workgroup 0 records the trace and
+// clears the failure flag for the panels that follow.
+__global__ __launch_bounds__(256) void k_ms_load(int H, const float* __restrict__ Bup,
+                                                 MstepHdr* __restrict__ hdr,
+                                                 double* __restrict__ M) {
+  __shared__ double red[4];
   double t = 0.0;
-  for (int h = threadIdx.x; h < H; h += 1024) {
+  for (int h = threadIdx.x; h < H; h += 256) {
     const float b = Bup[(int64_t)h * H + h];
     if (b > 0.0f) t += (double)b;
   }
   t = wave_sum_d(t);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += red[w];
-    hdr->trB = s;
+  const double trB = ((red[0] + red[1]) + red[2]) + red[3];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->trB = trB;
     hdr->failed = 0;
   }
-}
-
-// M = symmetrised active block of B (+ jitter), identity on inactive latents.
-__global__ __launch_bounds__(256) void k_ms_load(int H, const float* __restrict__ Bup,
-                                                 const MstepHdr* __restrict__ hdr,
-                                                 double* __restrict__ M) {
-  const double jitter = 1e-12 * (hdr->trB > 0.0 ? hdr->trB / H : 1.0);
+  const double jitter = 1e-12 * (trB > 0.0 ? trB / H : 1.0);
   const int64_t HH = (int64_t)H * H;
   // unconditional loads (upper-triangle element, both diagonals) so that
   // the unrolled iterations keep their loads in flight together
@@ -147,13 +147,17 @@ __device__ __forceinline__ void factor_rows(double (&a)[NBK], int lane, double* 
 // L_kk in one wave's registers, then solve this workgroup's 64 rows below,
 // L[i, kb:kb+nb] L_kk^T = M[i, kb:kb+nb], by forward substitution, one
 // thread per row (the rows' chains run side by side).  Every workgroup
-// factors the (small) diagonal block itself; workgroup 0 writes the block and
-// its mirror.  Each row below is written to the lower triangle and mirrored
-// into the upper one, so that both substitutions of the solve read coalesced
-// rows.  The inverses of the diagonal blocks, which only the solve needs, are
-// formed afterwards for all blocks at once (k_ms_invdiag), off the chain of
-// panels.
+// factors the (small) diagonal block itself.  Beside the rows below, wave 1
+// of workgroup 0 inverts L_kk (column j of L_kk^-1 by forward substitution
+// down the rows, lane j) and writes the inverse row-major (Dinv) and
+// transposed (DinvT) for the solve: that is all that is kept of the diagonal
+// block, whose place in M is left as it was (nothing reads it afterwards,
+// and other workgroups may still be loading it).  Each row below is written
+// to the lower triangle and mirrored into the upper one, so that both
+// substitutions of the solve read coalesced rows.
 __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restrict__ M,
+                                                  double* __restrict__ Dinv,
+                                                  double* __restrict__ DinvT,
                                                   MstepHdr* __restrict__ hdr) {
   __shared__ double Ls[NB][NB + 1];  // L_kk, row-major (lower)
   __shared__ double inv_s[NB];
@@ -181,15 +185,27 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     if (blockIdx.x == 0 && bad && lane == 0) hdr->failed = 1;
   }
   __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      if (r < nb && c <= r) {
-        const double v = Ls[r][c];
-        M[(int64_t)(kb + r) * H + kb + c] = v;
-        M[(int64_t)(kb + c) * H + kb + r] = v;
-      }
-    }
+  if (blockIdx.x == 0 && tid >= 64 && tid < 128) {
+    const int64_t blk = (int64_t)(kb / NB) * NB * NB;
+    double x[NB];
+    static_for<0, NB>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      __builtin_amdgcn_sched_barrier(0);
+      double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+      static_for<0, i>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        if constexpr ((m & 1) == 0) s0 = fma(-Ls[i][m], x[m], s0);
+        else s1 = fma(-Ls[i][m], x[m], s1);
+      });
+      x[i] = (s0 + s1) * inv_s[i];
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, NB>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      Dinv[blk + i * NB + lane] = x[i];   // Dinv[i][lane] = L_kk^-1[i][lane]
+      DinvT[blk + lane * NB + i] = x[i];  // DinvT[lane][i]
+    });
+    return;
   }
   // rows below the block exist only when the block is full (nb == 64); one
   // wave of them per workgroup (more waves sharing the broadcast reads of L
@@ -220,48 +236,6 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     constexpr int c = decltype(cc)::value;
     xp[c] = x[c];
     M[(int64_t)(kb + c) * H + i] = x[c];
-  });
-}
-
-// The inverses of the diagonal blocks of L (one workgroup of one wave per
-// block, all blocks at once): column j of L_bb^-1 by forward substitution
-// down the rows, lane j; written row-major (Dinv) and transposed (DinvT).
-// Padding rows and columns of a last partial block are the identity.
-__global__ __launch_bounds__(64) void k_ms_invdiag(int H, const double* __restrict__ M,
-                                                   double* __restrict__ Dinv,
-                                                   double* __restrict__ DinvT) {
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double inv_s[NB];
-  const int b = blockIdx.x, kb = b * NB, nb = min(NB, H - kb);
-  const int lane = threadIdx.x;
-  {
-    const double* rp = M + (int64_t)min(kb + lane, H - 1) * H + kb;
-    static_for<0, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      const double v = rp[c < nb ? c : 0];
-      Ls[lane][c] = (lane < nb && c < nb) ? ((c <= lane) ? v : 0.0) : (c == lane ? 1.0 : 0.0);
-    });
-  }
-  __syncthreads();
-  inv_s[lane] = 1.0 / Ls[lane][lane];
-  __syncthreads();
-  double x[NB];
-  static_for<0, NB>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    __builtin_amdgcn_sched_barrier(0);
-    double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
-    static_for<0, i>([&](auto mc) {
-      constexpr int m = decltype(mc)::value;
-      if constexpr ((m & 1) == 0) s0 = fma(-Ls[i][m], x[m], s0);
-      else s1 = fma(-Ls[i][m], x[m], s1);
-    });
-    x[i] = (s0 + s1) * inv_s[i];
-  });
-  __builtin_amdgcn_sched_barrier(0);
-  static_for<0, NB>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    Dinv[(int64_t)b * NB * NB + i * NB + lane] = x[i];   // Dinv[i][lane] = Linv[i][lane]
-    DinvT[(int64_t)b * NB * NB + lane * NB + i] = x[i];  // DinvT[lane][i]
   });
 }
 
@@ -314,16 +288,21 @@ __global__ __launch_bounds__(256) void k_ms_syrk(int H, int kb, double* __restri
   }
 }
 
-// x = B^-1 a_d for pixel d = 4 blockIdx.x + wave (one wave per pixel), with
-// the factor B = L L^T and the inverses of its 64 x 64 diagonal blocks:
+// x = B^-1 a_d for the SP pixels d = SP blockIdx.x + p, with the factor
+// B = L L^T and the inverses of its 64 x 64 diagonal blocks:
 //   forward   y_b = L_bb^-1 (a_b - sum_{k<b} L_bk y_k)
 //   backward  x_b = L_bb^-T (y_b - sum_{k>b} L_kb^T x_k)
-// Lane l owns row 64 b + l of each block step; the vector lives in LDS and is
-// read by broadcast.  L_bk (k < b) is read from its mirror in the upper
-// triangle and L_kb^T (k > b) from the lower one, so every matrix read of a
-// wave is one coalesced 512-byte row.  There is no scalar dependent chain:
-// each block step is a few matrix-vector products.  Writes row d of W_new and
-// the wave's part of tr(W_new^T A).
+// Lane l owns row 64 b + l of each block step, for all SP pixels at once, so
+// that every matrix element is loaded once per workgroup and serves the SP
+// vectors (kept in LDS, read by broadcast).  The sum over the columns of a
+// block step is split into quarters, one per wave; the partial sums are added
+// in wave order and wave p finishes pixel p.  L_bk (k < b) is read from its
+// mirror in the upper triangle and L_kb^T (k > b) from the lower one, so every
+// matrix read of a wave is one coalesced 512-byte row; each wave's quarter of
+// the diagonal block's inverse is loaded at the start of the step, with the
+// off-diagonal rows.  Writes row d of W_new and its part of tr(W_new^T A).
+constexpr int SP = 4;  // pixels per workgroup, one per wave
+
 __global__ __launch_bounds__(256) void k_ms_solve(int D, int H, const float* __restrict__ A,
                                                   const float* __restrict__ Bup,
                                                   const double* __restrict__ M,
@@ -332,76 +311,92 @@ __global__ __launch_bounds__(256) void k_ms_solve(int D, int H, const float* __r
                                                   const MstepHdr* __restrict__ hdr,
                                                   const float* W_old, float* W_new,
                                                   double* __restrict__ trp) {
-  extern __shared__ double xs_all[];  // [4][Hpad + 64]: the vector, then a 64-entry buffer
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  extern __shared__ double sm_solve[];
+  constexpr int Q = NB / 4;  // each wave's share of a diagonal block's columns
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Hpad = round_up(H, NB), nblk = Hpad / NB;
-  double* x = xs_all + (size_t)wave * (Hpad + NB);
-  double* t = x + Hpad;
-  const int d = blockIdx.x * 4 + wave;
-  const bool dok = d < D;
-  const int64_t row = (int64_t)(dok ? d : 0) * H;
+  double* xs = sm_solve;             // [SP][Hpad]   the vectors
+  double* red = xs + SP * Hpad;      // [4][SP][64]  the waves' partial sums
+  double* tb = red + 4 * SP * NB;    // [SP][64]     right-hand side of the diagonal step
+  const int d0 = blockIdx.x * SP;
   const bool failed = hdr->failed != 0;
-  for (int h = lane; h < Hpad; h += 64) {
+  for (int e = tid; e < SP * Hpad; e += 256) {
+    const int p = e / Hpad, h = e - p * Hpad;
+    const int d = min(d0 + p, D - 1);
     const int hc = h < H ? h : 0;
     const bool act = h < H && Bup[(int64_t)hc * H + hc] > 0.0f;
-    const float a = A[row + hc];
-    x[h] = act ? (double)a : 0.0;
+    const float a = A[(int64_t)d * H + hc];
+    xs[e] = act ? (double)a : 0.0;
   }
   __syncthreads();
-  // forward
-  for (int b = 0; b < nblk; ++b) {
+  // one block step: t = x_b - sum_j L(r, j) x_j over [j0, j1) split over the
+  // waves, then x_b = Dg t with this wave's quarter dv of the diagonal factor
+  auto step = [&](int b, int j0, int j1, const double* Dg) {
     const int r = NB * b + lane;
     const int rc = r < H ? r : H - 1;
-    double s0 = x[r], s1 = 0.0;
-    for (int k = 0; k < b; ++k) {
-      const double* Mk = M + (int64_t)NB * k * H + rc;  // M[64k + m][r] = L[r][64k + m]
-#pragma unroll 8
-      for (int m = 0; m < NB; m += 2) {
-        s0 = fma(-Mk[(int64_t)m * H], x[NB * k + m], s0);
-        s1 = fma(-Mk[(int64_t)(m + 1) * H], x[NB * k + m + 1], s1);
+    double dv[Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u) dv[u] = Dg[(int64_t)(Q * wave + u) * NB + lane];
+    double acc[SP];
+#pragma unroll
+    for (int p = 0; p < SP; ++p) acc[p] = 0.0;
+    const int q = (j1 - j0 + 3) / 4;
+    const int ja = j0 + wave * q, jb = min(ja + q, j1);
+    // chunks of 16 rows whose loads are all issued before the first product
+    // (addresses clamped into the range, values masked)
+    for (int j = ja; j < jb; j += 16) {
+      double mv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int jj = min(j + u, jb - 1);
+        const double v = M[(int64_t)jj * H + rc];
+        mv[u] = j + u < jb ? v : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int jj = min(j + u, jb - 1);
+#pragma unroll
+        for (int p = 0; p < SP; ++p) acc[p] = fma(-mv[u], xs[p * Hpad + jj], acc[p]);
       }
     }
-    t[lane] = r < H ? s0 + s1 : 0.0;
+#pragma unroll
+    for (int p = 0; p < SP; ++p) red[(wave * SP + p) * NB + lane] = acc[p];
     __syncthreads();
-    const double* Dt = DinvT + (int64_t)b * NB * NB + lane;  // DinvT[m][l] = Linv[l][m]
-    double y0 = 0.0, y1 = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < NB; m += 2) {
-      y0 = fma(Dt[m * NB], t[m], y0);
-      y1 = fma(Dt[(m + 1) * NB], t[m + 1], y1);
+    {
+      double t = xs[wave * Hpad + r];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) t += red[(w * SP + wave) * NB + lane];
+      tb[wave * NB + lane] = r < H ? t : 0.0;
     }
-    x[r] = y0 + y1;
     __syncthreads();
-  }
-  // backward
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int r = NB * b + lane;
-    const int rc = r < H ? r : H - 1;
-    double s0 = x[r], s1 = 0.0;
-    for (int k = b + 1; k < nblk; ++k) {
-      const int kmax = min(NB, H - NB * k);
-      const double* Mk = M + (int64_t)NB * k * H + rc;  // M[64k + m][r] = L[64k + m][r]
-      int m = 0;
-#pragma unroll 4
-      for (; m + 1 < kmax; m += 2) {
-        s0 = fma(-Mk[(int64_t)m * H], x[NB * k + m], s0);
-        s1 = fma(-Mk[(int64_t)(m + 1) * H], x[NB * k + m + 1], s1);
-      }
-      if (m < kmax) s0 = fma(-Mk[(int64_t)m * H], x[NB * k + m], s0);
+#pragma unroll
+    for (int p = 0; p < SP; ++p) acc[p] = 0.0;
+#pragma unroll
+    for (int u = 0; u < Q; ++u)
+#pragma unroll
+      for (int p = 0; p < SP; ++p) acc[p] = fma(dv[u], tb[p * NB + Q * wave + u], acc[p]);
+#pragma unroll
+    for (int p = 0; p < SP; ++p) red[(wave * SP + p) * NB + lane] = acc[p];
+    __syncthreads();
+    {
+      double y = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) y += red[(w * SP + wave) * NB + lane];
+      xs[wave * Hpad + r] = y;
     }
-    t[lane] = r < H ? s0 + s1 : 0.0;
     __syncthreads();
-    const double* Dr = Dinv + (int64_t)b * NB * NB + lane;  // Dinv[m][l] = Linv[m][l]
-    double y0 = 0.0, y1 = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < NB; m += 2) {
-      y0 = fma(Dr[m * NB], t[m], y0);
-      y1 = fma(Dr[(m + 1) * NB], t[m + 1], y1);
-    }
-    x[r] = y0 + y1;
-    __syncthreads();
-  }
-  if (!dok) return;
+  };
+  // forward: rows of L_bk (k < b) from the mirror, M[j][r] = L[r][j];
+  // DinvT[m][l] = L_bb^-1[l][m]
+  for (int b = 0; b < nblk; ++b) step(b, 0, NB * b, DinvT + (int64_t)b * NB * NB);
+  // backward: M[j][r] = L[j][r] for j beyond the block; Dinv[m][l] = L_bb^-1[m][l]
+  for (int b = nblk - 1; b >= 0; --b) step(b, NB * (b + 1) < H ? NB * (b + 1) : H, H,
+                                           Dinv + (int64_t)b * NB * NB);
+  const int d = d0 + wave;
+  if (d >= D) return;
+  const int64_t row = (int64_t)d * H;
+  const double* x = xs + wave * Hpad;
   if (failed) {
     for (int h = lane; h < H; h += 64) W_new[row + h] = W_old[row + h];
     if (lane == 0) trp[d] = 0.0;
@@ -631,7 +626,6 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
   if (is_max_model(model)) return hipSuccess;
   if (H > 16 * 64) return hipErrorInvalidValue;
   const MstepWork w = carve_mstep(work, D, H);
-  hipLaunchKernelGGL(k_ms_begin, dim3(1), dim3(1024), 0, st, H, B, w.hdr);
   const int64_t HH = (int64_t)H * H;
   // at most 32 workgroups: when B is factored beside the A statistics only
   // the CUs those leave out are free, and more workgroups than fit there
@@ -643,15 +637,14 @@ hipError_t launch_mstep_factor(int model, int D, int H, const float* B, void* wo
     const int nb = (H - kb < NB) ? H - kb : NB;
     const int below = H - kb - nb;
     const unsigned nblk = below > 0 ? (unsigned)((below + 63) / 64) : 1u;
-    hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.hdr);
+    hipLaunchKernelGGL(k_ms_panel, dim3(nblk), dim3(256), 0, st, H, kb, w.M, w.Dinv, w.DinvT,
+                       w.hdr);
     if (below > 0) {
       const int nt = (below + 31) / 32;
       hipLaunchKernelGGL(k_ms_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, H, kb,
                          w.M);
     }
   }
-  hipLaunchKernelGGL(k_ms_invdiag, dim3((unsigned)((H + NB - 1) / NB)), dim3(64), 0, st, H, w.M,
-                     w.Dinv, w.DinvT);
   return hipGetLastError();
 }
 
@@ -667,10 +660,10 @@ hipError_t launch_mstep_solve(int model, int D, int H, const float* A, const flo
   }
   if (H > 16 * 64) return hipErrorInvalidValue;
   const MstepWork w = carve_mstep(work, D, H);
-  const size_t lds = (size_t)4 * (round_up(H, NB) + NB) * 8;
+  const size_t lds = ((size_t)SP * round_up(H, NB) + 5 * SP * NB) * 8;
   hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(k_ms_solve), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ms_solve, dim3((unsigned)((D + 3) / 4)), dim3(256), lds, st, D, H, A, B,
+  hipLaunchKernelGGL(k_ms_solve, dim3((unsigned)((D + SP - 1) / SP)), dim3(256), lds, st, D, H, A, B,
                      w.M, w.Dinv, w.DinvT, w.hdr, W_old, W_new, w.trp);
   hipLaunchKernelGGL(k_ms_scalars_lin, dim3(1), dim3(256), 0, st, D, H, scal, w.trp, theta_new);
   return hipGetLastError();
