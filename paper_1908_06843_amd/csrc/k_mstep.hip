@@ -135,9 +135,44 @@ __device__ __forceinline__ void factor_rows(double (&a)[NBK], int lane, double* 
     myinv = (lane == k) ? inv : myinv;
     a[k] = (lane == k) ? dpos * inv : a[k] * inv;
     if (lane < NBK) col[lane] = a[k];
+    // every read of the column is issued before the first update, so that
+    // the reads overlap instead of each waiting out the LDS latency
+    double cr[NBK];
     static_for<k + 1, NBK>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      a[j] = fma(-a[k], col[j], a[j]);
+      cr[j] = col[j];
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<k + 1, NBK>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      a[j] = fma(-a[k], cr[j], a[j]);
+    });
+  });
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Forward substitution L_kk z = v for one vector per lane (v in z on entry),
+// by columns: once z_m is final its multiples are taken off all later
+// entries at once, so each step's chain is a single multiply and the updates
+// within a step are independent of each other.  LT[m][c] = L_kk[c][m] (read
+// by broadcast), inv[c] = 1 / L_kk[c][c].
+__device__ __forceinline__ void subst_cols(double (&z)[NB], const double (*LT)[NB],
+                                           const double* inv) {
+  static_for<0, NB>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+    // the step's reads first (they overlap), then its updates
+    __builtin_amdgcn_sched_barrier(0);
+    const double im = inv[m];
+    double cr[NB];
+    static_for<m + 1, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      cr[c] = LT[m][c];
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    z[m] *= im;
+    static_for<m + 1, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      z[c] = fma(-cr[c], z[m], z[c]);
     });
   });
   __builtin_amdgcn_sched_barrier(0);
@@ -146,10 +181,10 @@ __device__ __forceinline__ void factor_rows(double (&a)[NBK], int lane, double* 
 // Panel at kb (nb = min(64, H - kb) columns): factor the diagonal block
 // L_kk in one wave's registers, then solve this workgroup's 64 rows below,
 // L[i, kb:kb+nb] L_kk^T = M[i, kb:kb+nb], by forward substitution, one
-// thread per row (the rows' chains run side by side).  Every workgroup
-// factors the (small) diagonal block itself.  Beside the rows below, wave 1
-// of workgroup 0 inverts L_kk (column j of L_kk^-1 by forward substitution
-// down the rows, lane j) and writes the inverse row-major (Dinv) and
+// thread per row.  Every workgroup factors the (small) diagonal block
+// itself.  Beside the rows below, wave 1 of workgroup 0 inverts L_kk
+// (column j of L_kk^-1 by forward substitution of e_j, lane j; both
+// substitutions by columns) and writes the inverse row-major (Dinv) and
 // transposed (DinvT) for the solve: that is all that is kept of the diagonal
 // block, whose place in M is left as it was (nothing reads it afterwards,
 // and other workgroups may still be loading it).  Each row below is written
@@ -159,7 +194,7 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
                                                   double* __restrict__ Dinv,
                                                   double* __restrict__ DinvT,
                                                   MstepHdr* __restrict__ hdr) {
-  __shared__ double Ls[NB][NB + 1];  // L_kk, row-major (lower)
+  __shared__ double LsT[NB][NB];  // LsT[m][c] = L_kk[c][m] (upper part zero)
   __shared__ double inv_s[NB];
   __shared__ double colb[NB];
   const int nb = min(NB, H - kb);
@@ -179,7 +214,7 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     factor_rows<NB>(a, lane, colb, myinv, bad);
     static_for<0, NB>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
-      Ls[lane][c] = (c <= lane) ? a[c] : 0.0;
+      LsT[c][lane] = (c <= lane) ? a[c] : 0.0;
     });
     inv_s[lane] = myinv;
     if (blockIdx.x == 0 && bad && lane == 0) hdr->failed = 1;
@@ -190,16 +225,9 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     double x[NB];
     static_for<0, NB>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      __builtin_amdgcn_sched_barrier(0);
-      double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
-      static_for<0, i>([&](auto mc) {
-        constexpr int m = decltype(mc)::value;
-        if constexpr ((m & 1) == 0) s0 = fma(-Ls[i][m], x[m], s0);
-        else s1 = fma(-Ls[i][m], x[m], s1);
-      });
-      x[i] = (s0 + s1) * inv_s[i];
+      x[i] = i == lane ? 1.0 : 0.0;
     });
-    __builtin_amdgcn_sched_barrier(0);
+    subst_cols(x, LsT, inv_s);
     static_for<0, NB>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       Dinv[blk + i * NB + lane] = x[i];   // Dinv[i][lane] = L_kk^-1[i][lane]
@@ -219,19 +247,8 @@ __global__ __launch_bounds__(256) void k_ms_panel(int H, int kb, double* __restr
     constexpr int c = decltype(cc)::value;
     x[c] = xp[c];
   });
-  // x_c = (M[i][c] - sum_{m<c} L[c][m] x_m) / L[c][c]
-  static_for<0, NB>([&](auto cc) {
-    constexpr int c = decltype(cc)::value;
-    __builtin_amdgcn_sched_barrier(0);
-    double s0 = x[c], s1 = 0.0;
-    static_for<0, c>([&](auto mc) {
-      constexpr int m = decltype(mc)::value;
-      if constexpr ((m & 1) == 0) s0 = fma(-Ls[c][m], x[m], s0);
-      else s1 = fma(-Ls[c][m], x[m], s1);
-    });
-    x[c] = (s0 + s1) * inv_s[c];
-  });
-  __builtin_amdgcn_sched_barrier(0);
+  // L_kk x = M[i, kb:kb+64]^T
+  subst_cols(x, LsT, inv_s);
   static_for<0, NB>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     xp[c] = x[c];
