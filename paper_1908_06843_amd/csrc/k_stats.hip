@@ -365,6 +365,40 @@ struct SliceRows {
   int r0[STATS_MAX_BSLICES + 1];
 };
 
+// B alone (A reduced by its own kernel): B[h][h2] += sum_g partB[g][slice(h)][...]
+// for h2 >= h, four threads per element, each summing a quarter of the
+// partials with 16 loads in flight; the four sums are added in quarter order.
+__global__ __launch_bounds__(256) void k_stats_reduce_B(int H, int nB, SliceRows rows, int ngB,
+                                                        const float* __restrict__ partB,
+                                                        float* __restrict__ B) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t f = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = f < (int64_t)H * H;
+  const int h = ok ? (int)(f / H) : 0, h2 = ok ? (int)(f % H) : 0;
+  const bool up = ok && h2 >= h;
+  double acc = 0.0;
+  if (up) {
+    int b = 0;
+    while (b + 1 < nB && h >= rows.r0[b + 1]) ++b;
+    const int idx = bslice_off(H, rows.r0[b], h) + (h2 - h);
+    const int per = (ngB + 3) / 4;
+    const int g0 = q * per, g1 = min(g0 + per, ngB);
+    int g = g0;
+    for (; g + 16 <= g1; g += 16) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = partB[((int64_t)(g + u) * nB + b) * BSLICE_MAX + idx];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    for (; g < g1; ++g) acc += partB[((int64_t)g * nB + b) * BSLICE_MAX + idx];
+  }
+  red[q][lane] = acc;
+  __syncthreads();
+  if (q == 0 && up) B[f] += (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+}
+
 __global__ __launch_bounds__(256) void k_stats_reduce(int D, int H, int DS, int nA, int nB,
                                                       SliceRows rows, int ngA, int ngB,
                                                       const float* __restrict__ partA,
@@ -469,10 +503,15 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
       bslice_bounds(H, b, &r0, &r1);
       rows.r0[b] = r0;
     }
+    if (!with_A) {
+      const int64_t HH = (int64_t)H * H;
+      hipLaunchKernelGGL(k_stats_reduce_B, dim3((unsigned)((HH + 63) / 64)), dim3(256), 0, st, H,
+                         nB, rows, ngB, s.partB, B);
+      return hipGetLastError();
+    }
     const int64_t tot = (int64_t)D * H + (int64_t)H * H;
     hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D,
-                       H, pl.DS, pl.nA, nB, rows, with_A ? pl.ngroups : 0, ngB, s.partA, s.partB,
-                       with_A ? A : nullptr, B);
+                       H, pl.DS, pl.nA, nB, rows, pl.ngroups, ngB, s.partA, s.partB, A, B);
     return hipGetLastError();
   };
   if (mfmaA) {
