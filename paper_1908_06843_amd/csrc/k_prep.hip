@@ -117,9 +117,13 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, 
 // of a chunk are staged in LDS by one load phase, the four waves take 64 rows
 // each (every lane a 2 x 2 block of the tile), and the four partial tiles are
 // summed in wave order at the end.  zB (optional): the H x H accumulator
-// cleared on the way.
+// cleared on the way.  hn_hi (optional): the diagonal also gives
+// hn[h] = 1/2 ||W_h||^2 (FP64 head and tail) and the running max of ||W_h||_2,
+// as k_norms forms them for P = W.
 __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D, int H,
-                                              float* __restrict__ G, float* __restrict__ zB) {
+                                              float* __restrict__ G, float* __restrict__ zB,
+                                              float* __restrict__ hn_hi, float* __restrict__ hn_lo,
+                                              float* __restrict__ pnorm) {
   constexpr int KC = 256;
   __shared__ float a[KC][16], b[KC][16];  // a[k][c] = W[d0 + k][i0 + c], b likewise at j0
   __shared__ double part[4][16][16];
@@ -161,6 +165,13 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D
     const double g = ((part[0][ti][tj] + part[1][ti][tj]) + part[2][ti][tj]) + part[3][ti][tj];
     G[(int64_t)i * H + j] = (float)g;
     if (zB) zB[(int64_t)i * H + j] = 0.0f;
+    if (hn_hi && i == j) {
+      const double half = 0.5 * g;
+      const float hi = (float)half;
+      hn_hi[i] = hi;
+      hn_lo[i] = (float)(half - (double)hi);
+      atomicMax(reinterpret_cast<unsigned int*>(pnorm), __float_as_uint((float)sqrt(g)));
+    }
   }
 }
 
@@ -205,18 +216,21 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
                      prec != PROSPER_FP32 ? p.Pt_hi : nullptr,
                      prec != PROSPER_FP32 ? p.Pt_lo : nullptr, z.A, z.B_dh ? z.B : nullptr);
   if (!is_max_model(model)) {
+    // P = W: the norms come from the Gram diagonal
     dim3 gg((H + 15) / 16, (H + 15) / 16);
-    hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G, z.B_dh ? nullptr : z.B);
+    hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G, z.B_dh ? nullptr : z.B,
+                       p.hn_hi, p.hn_lo, p.pnorm);
+  } else {
+    hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi,
+                       p.hn_lo, p.pnorm);
   }
-  hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi, p.hn_lo,
-                     p.pnorm);
   if (model == PROSPER_MCA)
     hipLaunchKernelGGL(k_rowmax, dim3((D + 255) / 256), dim3(256), 0, st, W, D, H, p.wmax);
   return hipGetLastError();
 }
 
 // Separate entry so that the theta kernel (which also clears pnorm) runs
-// before k_norms on the same stream.
+// before the kernel that forms the norms (k_gram or k_norms) on the same stream.
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
                              hipStream_t st, int32_t* defer_count, float beta,
