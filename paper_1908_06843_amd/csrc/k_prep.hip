@@ -76,14 +76,12 @@ __global__ void k_theta(int model, int D, int H, double pi_h, double sigma_h,
 // Pt32[h][d] = P[d][h] (zero for d >= D), P = W or max(W, 0) (MCA, H > 1);
 // optional BF16 head/tail split.  32 x 32 tiles through LDS.
 // zA, zB (optional): D x H accumulators cleared on the way (same index map as W).
-__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, int D, int H,
-                                                   int Dp, int relu, float* __restrict__ Pt32,
-                                                   bf16* __restrict__ Pt_hi,
-                                                   bf16* __restrict__ Pt_lo,
-                                                   float* __restrict__ zA,
-                                                   float* __restrict__ zB) {
+__device__ __forceinline__ void transpose_tile(int bx, int by, const float* __restrict__ W, int D,
+                                               int H, int Dp, int relu, float* __restrict__ Pt32,
+                                               bf16* __restrict__ Pt_hi, bf16* __restrict__ Pt_lo,
+                                               float* __restrict__ zA, float* __restrict__ zB) {
   __shared__ float tile[32][33];
-  const int d0 = blockIdx.x * 32, h0 = blockIdx.y * 32;
+  const int d0 = bx * 32, h0 = by * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int r = ty; r < 32; r += 8) {
     int d = d0 + r, h = h0 + tx;
@@ -112,6 +110,15 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, 
   }
 }
 
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, int D, int H,
+                                                   int Dp, int relu, float* __restrict__ Pt32,
+                                                   bf16* __restrict__ Pt_hi,
+                                                   bf16* __restrict__ Pt_lo,
+                                                   float* __restrict__ zA,
+                                                   float* __restrict__ zB) {
+  transpose_tile(blockIdx.x, blockIdx.y, W, D, H, Dp, relu, Pt32, Pt_hi, Pt_lo, zA, zB);
+}
+
 // G[i][j] = sum_d W[d][i] W[d][j], FP64 accumulation, one 16 x 16 output tile
 // per workgroup.  Depth goes in chunks of 256 rows of W: both 16-column slabs
 // of a chunk are staged in LDS by one load phase, the four waves take 64 rows
@@ -120,14 +127,14 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ W, 
 // cleared on the way.  hn_hi (optional): the diagonal also gives
 // hn[h] = 1/2 ||W_h||^2 (FP64 head and tail) and the running max of ||W_h||_2,
 // as k_norms forms them for P = W.
-__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D, int H,
-                                              float* __restrict__ G, float* __restrict__ zB,
-                                              float* __restrict__ hn_hi, float* __restrict__ hn_lo,
-                                              float* __restrict__ pnorm) {
+__device__ __forceinline__ void gram_tile(int bx, int by, const float* __restrict__ W, int D, int H,
+                                          float* __restrict__ G, float* __restrict__ zB,
+                                          float* __restrict__ hn_hi, float* __restrict__ hn_lo,
+                                          float* __restrict__ pnorm) {
   constexpr int KC = 256;
   __shared__ float a[KC][16], b[KC][16];  // a[k][c] = W[d0 + k][i0 + c], b likewise at j0
   __shared__ double part[4][16][16];
-  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int i0 = by * 16, j0 = bx * 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = (lane >> 3) * 2, c = (lane & 7) * 2;
   double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
@@ -175,6 +182,22 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ W, int D
   }
 }
 
+// Linear models: the transpose and the Gram matrix in one launch (both only
+// read W).  Workgroups [0, ntx * nty) take the 32 x 32 transpose tiles, the
+// rest the 16 x 16 Gram tiles (ngx per row).
+__global__ __launch_bounds__(256) void k_transpose_gram(
+    const float* __restrict__ W, int D, int H, int Dp, int ntx, int nty, int ngx,
+    float* __restrict__ Pt32, bf16* __restrict__ Pt_hi, bf16* __restrict__ Pt_lo,
+    float* __restrict__ zA, float* __restrict__ G, float* __restrict__ zB,
+    float* __restrict__ hn_hi, float* __restrict__ hn_lo, float* __restrict__ pnorm) {
+  const int nt = ntx * nty;
+  const int b = blockIdx.x;
+  if (b < nt)
+    transpose_tile(b % ntx, b / ntx, W, D, H, Dp, 0, Pt32, Pt_hi, Pt_lo, zA, nullptr);
+  else
+    gram_tile((b - nt) % ngx, (b - nt) / ngx, W, D, H, G, zB, hn_hi, hn_lo, pnorm);
+}
+
 // hn[h] = 1/2 ||P_h||^2 in FP64 split into an FP32 head and tail; running
 // max of ||P_h||_2 (positive floats order like their bit patterns).  One
 // wave per latent, lanes over pixels of the transposed (contiguous) row.
@@ -212,15 +235,17 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
                        const Prepared& p, hipStream_t st, const AccZero& z) {
   const int relu = (model == PROSPER_MCA && H > 1) ? 1 : 0;
   dim3 gt((Dp + 31) / 32, (H + 31) / 32);
-  hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, st, W, D, H, Dp, relu, p.Pt32,
-                     prec != PROSPER_FP32 ? p.Pt_hi : nullptr,
-                     prec != PROSPER_FP32 ? p.Pt_lo : nullptr, z.A, z.B_dh ? z.B : nullptr);
-  if (!is_max_model(model)) {
-    // P = W: the norms come from the Gram diagonal
-    dim3 gg((H + 15) / 16, (H + 15) / 16);
-    hipLaunchKernelGGL(k_gram, gg, dim3(256), 0, st, W, D, H, p.G, z.B_dh ? nullptr : z.B,
-                       p.hn_hi, p.hn_lo, p.pnorm);
+  bf16* hi = prec != PROSPER_FP32 ? p.Pt_hi : nullptr;
+  bf16* lo = prec != PROSPER_FP32 ? p.Pt_lo : nullptr;
+  if (!is_max_model(model) && !z.B_dh) {
+    // P = W: one launch for the transpose and G; the norms come from G's diagonal
+    const int ngx = (H + 15) / 16;
+    const unsigned nblk = gt.x * gt.y + (unsigned)(ngx * ngx);
+    hipLaunchKernelGGL(k_transpose_gram, dim3(nblk), dim3(256), 0, st, W, D, H, Dp, (int)gt.x,
+                       (int)gt.y, ngx, p.Pt32, hi, lo, z.A, p.G, z.B, p.hn_hi, p.hn_lo, p.pnorm);
   } else {
+    hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, st, W, D, H, Dp, relu, p.Pt32, hi, lo, z.A,
+                       z.B_dh ? z.B : nullptr);
     hipLaunchKernelGGL(k_norms, dim3((H + 3) / 4), dim3(256), 0, st, p.Pt32, Dp, H, p.hn_hi,
                        p.hn_lo, p.pnorm);
   }
@@ -230,7 +255,7 @@ hipError_t launch_prep(int model, int prec, const float* W, int D, int H, int Dp
 }
 
 // Separate entry so that the theta kernel (which also clears pnorm) runs
-// before the kernel that forms the norms (k_gram or k_norms) on the same stream.
+// before the kernel that forms the norms (k_transpose_gram or k_norms) on the same stream.
 hipError_t launch_theta_full(int model, int D, int H, double pi, double sigma,
                              const double* theta_dev, const Prepared& p, int32_t* redo_count,
                              hipStream_t st, int32_t* defer_count, float beta,
