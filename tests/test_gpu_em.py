@@ -156,10 +156,13 @@ def test_em_bars_trajectory_and_monotone_free_energy():
     assert rel(Wd.cpu().numpy(), W_ref) < 1e-3
 
 
-@pytest.mark.parametrize("H,D,inactive", [(320, 96, (5, 130, 319)), (64, 40, ()), (200, 256, (0, 199))])
+@pytest.mark.parametrize("H,D,inactive", [(320, 96, (5, 130, 319)), (64, 40, ()), (200, 256, (0, 199)),
+                                           (455, 70, (0, 300, 454)), (1024, 33, (17,))])
 def test_mstep_solve_many_panels(H, D, inactive):
     """The blocked FP64 solve over several 64-column panels (ragged last
-    panel, inactive latents inside and at the ends) against the plain
+    panel, up to the largest H of 16 panels, pixel counts that leave the last
+    group of four pixels partly empty, inactive latents inside and at the
+    ends) against the plain
     definition W = A B^-1 on the active block (numpy's dense solve), and
     sigma^2 = (sum||y||^2 - tr(W^T A)) / (N D), pi = sum<k> / (N H)."""
     import torch
@@ -174,14 +177,16 @@ def test_mstep_solve_many_panels(H, D, inactive):
     act = np.diag(B) > 0
     W_old = g.standard_normal((D, H)).astype(np.float32)
     N = 5000.0
-    scal = np.array([7.0 * N / 10, -1e5, 50.0 * N * D / 10, 0.0, N])
     Wr = W_old.astype(np.float64).copy()
     Bf = np.triu(B).astype(np.float32)
     Bs = np.triu(Bf).astype(np.float64)
     Bs = Bs + np.triu(Bs, 1).T
     Af = A.astype(np.float32).astype(np.float64)
     Wr[:, act] = np.linalg.solve(Bs[np.ix_(act, act)], Af[:, act].T).T
-    s2 = (scal[2] - float((Wr[:, act] * Af[:, act]).sum())) / (N * D)
+    trWA = float((Wr[:, act] * Af[:, act]).sum())
+    # sum ||y||^2 consistent with the statistics: sigma^2 = 5 exactly
+    scal = np.array([7.0 * N / 10, -1e5, trWA + 5.0 * N * D, 0.0, N])
+    s2 = (scal[2] - trWA) / (N * D)
     dev = torch.device("cuda", 0)
     acc = {"A": torch.tensor(A, dtype=torch.float32, device=dev),
            "B": torch.tensor(Bf, device=dev),
