@@ -436,8 +436,8 @@ def measured_traffic(kernel):
 def pmc_pass():
     """Short run for hardware-counter passes: one device copy of a known size
     (the scale reference for the byte counters), two BF16 E-steps with
-    statistics at BSC scale, then one E-step with statistics on each of the
-    MCA, TSC and DSC workloads."""
+    statistics at BSC scale and the M-step from their statistics, then one
+    E-step with statistics on each of the MCA, TSC and DSC workloads."""
     import torch
     import synth
     from paper_1908_06843_amd import api
@@ -456,6 +456,7 @@ def pmc_pass():
         api.zero_acc(acc)
         api.estep(Yd, Wd, pi0, s0, Hprime=wl.Hprime, gamma=wl.gamma, precision="bf16", acc=acc,
                   want=(), ctx=ctx)
+    api.mstep(acc, Wd, model="bsc", ctx=ctx)
     torch.cuda.synchronize()
     # one E-step with statistics on each of the MCA and TSC workloads
     for name, prec in (("mca", "fp32"), ("tsc", "bf16")):
