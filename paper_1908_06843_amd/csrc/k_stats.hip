@@ -366,19 +366,31 @@ struct SliceRows {
 };
 
 // B alone (A reduced by its own kernel): B[h][h2] += sum_g partB[g][slice(h)][...]
-// for h2 >= h, four threads per element, each summing a quarter of the
+// for h2 >= h.  Threads run over the packed upper triangle (row h starts at
+// h H - h (h - 1) / 2), four per element, each summing a quarter of the
 // partials with 16 loads in flight; the four sums are added in quarter order.
+__device__ __forceinline__ int64_t tri_row_start(int H, int h) {
+  return (int64_t)h * H - (int64_t)h * (h - 1) / 2;
+}
+
 __global__ __launch_bounds__(256) void k_stats_reduce_B(int H, int nB, SliceRows rows, int ngB,
                                                         const float* __restrict__ partB,
                                                         float* __restrict__ B) {
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t f = (int64_t)blockIdx.x * 64 + lane;
-  const bool ok = f < (int64_t)H * H;
-  const int h = ok ? (int)(f / H) : 0, h2 = ok ? (int)(f % H) : 0;
-  const bool up = ok && h2 >= h;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = e < (int64_t)H * (H + 1) / 2;
   double acc = 0.0;
-  if (up) {
+  int h = 0, h2 = 0;
+  if (ok) {
+    // the row: the largest h with tri_row_start(h) <= e (root of the
+    // quadratic, then corrected in integers)
+    const double Hh = (double)H + 0.5;
+    h = (int)(Hh - sqrt(Hh * Hh - 2.0 * (double)e));
+    h = min(max(h, 0), H - 1);
+    while (h > 0 && tri_row_start(H, h) > e) --h;
+    while (h + 1 < H && tri_row_start(H, h + 1) <= e) ++h;
+    h2 = h + (int)(e - tri_row_start(H, h));
     int b = 0;
     while (b + 1 < nB && h >= rows.r0[b + 1]) ++b;
     const int idx = bslice_off(H, rows.r0[b], h) + (h2 - h);
@@ -396,7 +408,9 @@ __global__ __launch_bounds__(256) void k_stats_reduce_B(int H, int nB, SliceRows
   }
   red[q][lane] = acc;
   __syncthreads();
-  if (q == 0 && up) B[f] += (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+  if (q == 0 && ok)
+    B[(int64_t)h * H + h2] +=
+        (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 __global__ __launch_bounds__(256) void k_stats_reduce(int D, int H, int DS, int nA, int nB,
@@ -504,8 +518,8 @@ hipError_t launch_stats(const float* Y, int64_t N, int D, int H, int Hp, const S
       rows.r0[b] = r0;
     }
     if (!with_A) {
-      const int64_t HH = (int64_t)H * H;
-      hipLaunchKernelGGL(k_stats_reduce_B, dim3((unsigned)((HH + 63) / 64)), dim3(256), 0, st, H,
+      const int64_t np = (int64_t)H * (H + 1) / 2;
+      hipLaunchKernelGGL(k_stats_reduce_B, dim3((unsigned)((np + 63) / 64)), dim3(256), 0, st, H,
                          nB, rows, ngB, s.partB, B);
       return hipGetLastError();
     }
